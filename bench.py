@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X MLFMA matvec (one GPU).
+
+A step is one full matvec phi = A q through the C ABI: gather, near-field
+P2P, C2M, M2M up the tree, M2L on every level, L2L down the tree, L2O and
+the scatter back to the caller's order.  Inputs are resident in HBM before
+the timed region; setup (tree, FP64 operator precompute, uploads) is timed
+separately.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--nrhs R] [--bf16x3] [--no-cpu-baseline]
+
+The default workload is the 262,144-point sphere of diameter 16 wavelengths,
+leaf 0.25 wavelength, 3 digits, one right-hand side.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3        # FP32 vector and FP32 matrix
+PEAK_BF16_TFLOPS = 2500.0       # dense BF16 MFMA
+
+# bound of each kernel as implemented
+BOUND = {"gather": "hbm", "p2p": "alu", "c2m": "alu", "interp_s1": "alu",
+         "interp_s2": "alu", "interp_s3": "alu", "m2l": "hbm", "anterp_s1": "alu",
+         "anterp_s2": "alu", "anterp_s3": "alu", "l2o": "alu"}
+
+
+def algorithmic_work(tinfo, levels, R):
+    """Algorithmic bytes and flops of each kernel for one step with R
+    right-hand sides (complex64 = 8 bytes; a complex multiply-add = 8 flops;
+    a complex-by-real multiply-add = 4 flops; sin, cos and rsqrt count as one
+    flop each).  Each quantity is the minimum the method must move or
+    compute, not what a kernel happens to do."""
+    N = tinfo["n_points"]
+    nl = tinfo["n_levels"]
+    lv = {d["level"]: d for d in levels}
+    w = {k: {"bytes": 0.0, "flops": 0.0} for k in BOUND}
+    w["gather"]["bytes"] = N * (16.0 * R + 4)
+    # per pair: 6 subtractions, 5 for r^2, rsqrt, r, k r, sin, cos, 2 scalings
+    # (17) plus a complex multiply-add per right-hand side
+    w["p2p"]["flops"] = tinfo["n_p2p_pairs"] * (17.0 + 8.0 * R)
+    w["p2p"]["bytes"] = N * (16.0 + 16.0 * R)
+    if nl >= 3:
+        Kl = lv[nl]["K"]
+        # per (point, sample): phase (5), sin + cos (2), complex MAC per RHS
+        w["c2m"]["flops"] = N * Kl * (7.0 + 8.0 * R)
+        w["c2m"]["bytes"] = N * (16.0 + 8.0 * R) + lv[nl]["nbox"] * R * Kl * 8.0
+        w["l2o"]["flops"] = N * Kl * (7.0 + 2.0 + 8.0 * R)
+        w["l2o"]["bytes"] = N * (16.0 + 24.0 * R) + lv[nl]["nbox"] * R * Kl * 8.0
+        for l in range(3, nl + 1):
+            d = lv[l]
+            w["m2l"]["bytes"] += 8.0 * R * d["nbox"] * d["K"] * 2 + 8.0 * d["n_types"] * d["K"] \
+                + 6.0 * d["n_far"]
+            w["m2l"]["flops"] += 8.0 * R * d["n_far"] * d["K"]
+        for l in range(3, nl):
+            p, c = lv[l], lv[l + 1]
+            M = 2 * c["L"] + 1
+            Bc, Bp = c["nbox"] * R, p["nbox"] * R
+            w["interp_s1"]["flops"] += 4.0 * Bc * c["ntheta"] * c["nphi"] * M
+            w["interp_s1"]["bytes"] += 8.0 * Bc * (c["K"] + c["ntheta"] * M)
+            w["interp_s2"]["flops"] += 4.0 * Bc * M * p["ntheta"] * c["ntheta"]
+            w["interp_s2"]["bytes"] += 8.0 * Bc * M * (c["ntheta"] + p["ntheta"])
+            w["interp_s3"]["flops"] += 4.0 * Bc * p["ntheta"] * M * p["nphi"] + 8.0 * Bc * p["K"]
+            w["interp_s3"]["bytes"] += 8.0 * (Bc * p["ntheta"] * M + Bp * p["K"])
+            w["anterp_s1"]["flops"] += 4.0 * Bc * p["ntheta"] * p["nphi"] * M + 8.0 * Bc * p["K"]
+            w["anterp_s1"]["bytes"] += 8.0 * (Bc * p["ntheta"] * M + Bp * p["K"])
+            w["anterp_s2"]["flops"] += 4.0 * Bc * M * c["ntheta"] * p["ntheta"]
+            w["anterp_s2"]["bytes"] += 8.0 * Bc * M * (c["ntheta"] + p["ntheta"])
+            w["anterp_s3"]["flops"] += 4.0 * Bc * c["ntheta"] * M * c["nphi"]
+            w["anterp_s3"]["bytes"] += 8.0 * Bc * (c["ntheta"] * M + 2 * c["K"])
+    return w
+
+
+def roofline(kernel, work, ms_per_step, launches_per_step, bf16x3):
+    bound = BOUND[kernel]
+    sec = ms_per_step * 1e-3
+    if bound == "hbm":
+        achieved = work["bytes"] / sec / 1e9
+        peak, unit = PEAK_HBM_GBS, "GB/s"
+    else:
+        achieved = work["flops"] / sec / 1e12
+        peak, unit = PEAK_FP32_TFLOPS, "TFLOP/s"
+        if bound == "mfma" and bf16x3:
+            peak = PEAK_BF16_TFLOPS
+    return {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
+            "launches_per_step": launches_per_step,
+            "avg_launch_us": round(1e3 * ms_per_step / max(1, launches_per_step), 3),
+            "ms_per_step": round(ms_per_step, 4)}
+
+
+def cpu_baseline(xyz, q, phi_gpu):
+    """The FP64 oracle MLFMA, untuned, timed on the host cores: one full
+    matvec of the same workload (setup excluded)."""
+    from oracle import dense
+    from oracle import mlfma as M
+    from paper_2006_15367_amd import workloads as W
+    tree = M.Tree(xyz, W.LEAF_SIZE)
+    ops = M.Operators(tree, W.K_WAVENUMBER, W.DIGITS)
+    t0 = time.perf_counter()
+    phi = M.matvec(tree, ops, q)
+    dt = time.perf_counter() - t0
+    R = 1 if q.ndim == 1 else q.shape[1]
+    err = float(np.linalg.norm(phi_gpu - phi) / np.linalg.norm(phi))
+    rng = np.random.default_rng(7)
+    idx = rng.choice(xyz.shape[0], min(1024, xyz.shape[0]), replace=False)
+    ref = dense.potential(xyz, q, W.K_WAVENUMBER, tgt=xyz[idx])
+    err_dense = float(np.linalg.norm(phi_gpu[idx] - ref) / np.linalg.norm(ref))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": round(xyz.shape[0] * R / dt, 1), "unit": "points/s", "cores": cores,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": "one full FP64 oracle MLFMA matvec of the same workload (numpy + C "
+                      "near field), setup excluded",
+            "gpu_rel_l2_vs_oracle_mlfma": err, "gpu_rel_l2_vs_dense_1024_targets": err_dense}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sphere262k")
+    ap.add_argument("--nrhs", type=int, default=None)
+    ap.add_argument("--bf16x3", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the multi-GPU path is not part of this "
+              "build (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_15367_amd import mlfma as G
+    from paper_2006_15367_amd import workloads as W
+
+    xyz, q = W.make(args.workload, nrhs=args.nrhs)
+    R = 1 if q.ndim == 1 else q.shape[1]
+    t0 = time.perf_counter()
+    tree = G.Tree(xyz, W.LEAF_SIZE)
+    t1 = time.perf_counter()
+    ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=args.bf16x3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tinfo = tree.info()
+    levels = ops.levels()
+    qd = torch.from_numpy(np.ascontiguousarray(q.astype(np.complex64))).cuda()
+    vd = torch.from_numpy(np.ascontiguousarray(np.conj(q).astype(np.complex64))).cuda()
+
+    for _ in range(args.warmup):
+        phi = ops.matvec(qd)
+    torch.cuda.synchronize()
+    # one profiled step picks the dominant kernel
+    ops.profile_begin(None, 4096)
+    ops.matvec(qd)
+    torch.cuda.synchronize()
+    per_kernel = ops.profile_end()
+    dominant = max(per_kernel, key=lambda k: per_kernel[k][0])
+    launches = per_kernel[dominant][1]
+
+    # timed region: K steps; HIP events bracket the dominant kernel's launches
+    ops.profile_begin([dominant], launches * args.steps + 16)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        phi = ops.matvec(qd)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    dom = ops.profile_end()[dominant]
+    ms_per_step = (te - ts) * 1e3 / args.steps
+
+    # adjoint, timed the same way (no events)
+    for _ in range(2):
+        ops.adjoint(vd)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        psi = ops.adjoint(vd)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - ta) * 1e3 / args.steps
+
+    work = algorithmic_work(tinfo, levels, R)
+    rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
+    value = xyz.shape[0] * R / (ms_per_step * 1e-3)
+    out = {
+        "metric": "MLFMA matvec points/s at 1e-3 rel-L2 (+adjoint)",
+        "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 (fp32)" + (" + bf16x3 interpolation" if args.bf16x3 else ""),
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_points": int(xyz.shape[0]), "nrhs": R,
+                   "k": W.K_WAVENUMBER, "leaf": W.LEAF_SIZE, "digits": W.DIGITS,
+                   "levels": tinfo["n_levels"], "parallelism": "single GPU"},
+        "adjoint": {"value": round(xyz.shape[0] * R / (adj_ms * 1e-3), 1),
+                    "ms_per_step": round(adj_ms, 4)},
+        "setup_s": {"tree": round(t1 - t0, 3), "operators": round(t2 - t1, 3)},
+        "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
+        "roofline": rl,
+    }
+    if not args.no_cpu_baseline:
+        phi_np = phi.cpu().numpy().astype(np.complex128)
+        out["cpu_baseline"] = cpu_baseline(xyz, q.astype(np.complex128), phi_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+/*
+ * mlfma.h -- C ABI of the MI355X (gfx950) MLFMA matvec for the Helmholtz
+ * potential
+ *
+ *     phi_i = sum_{j != i} q_j exp(i k |r_i - r_j|) / |r_i - r_j|,
+ *
+ * the pair-potential sum of the paper's problem statement (Sec. 2, Eq. for
+ * Phi(r)) with the kernel written exp(+ikr)/r (the paper's exp(-jkr)/(4 pi r)
+ * is its complex conjugate over 4 pi for real k; the adjoint entry point
+ * evaluates that convention up to the 1/(4 pi) factor).
+ *
+ * The library evaluates it with the multilevel fast multipole algorithm of
+ * the paper: an octree over the points (Sec. 2 FMM paragraph, Sec. 3.1),
+ * leaf plane-wave signatures (C2M, Sec. 3.2.1), interpolation + shift +
+ * aggregation up the tree (M2M, Sec. 3.2.2), diagonal translation over the
+ * far-field lists (M2L, Sec. 3.2.3), shift + anterpolation + aggregation down
+ * the tree (L2L, Sec. 3.2.4), evaluation at the leaf points (L2O, Sec. 3.2.5)
+ * and the direct near-field sum at the leaf level (Sec. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: MLFMA_OK (0) on success, a positive MLFMA_E* code otherwise.
+ *   The library never aborts and never prints; mlfma_last_error() returns a
+ *   thread-local text for the last failing call on the calling thread.
+ * - Host pointers are read during the call only; the library keeps copies.
+ * - Device pointers are caller-owned HIP device buffers on the device the
+ *   tree was built for.  Work is enqueued on `stream` (a hipStream_t, NULL =
+ *   the null stream) and is NOT complete when the call returns; the caller
+ *   synchronises the stream before reading results.
+ * - Complex arrays are interleaved (re, im); dtype MLFMA_C64 = float pairs,
+ *   MLFMA_C128 = double pairs (converted to and from FP32 inside the
+ *   kernels; the arithmetic is FP32 either way).
+ * - Per-point arrays are in the CALLER's point order, row-major
+ *   [n][nrhs] (column c = right-hand side c).
+ * - An operator handle owns one workspace: calls on one handle must not
+ *   overlap in time (different handles may run concurrently).
+ */
+#ifndef MLFMA_H
+#define MLFMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlfma_tree_s *mlfma_tree_t;
+typedef struct mlfma_ops_s *mlfma_ops_t;
+
+enum mlfma_status {
+    MLFMA_OK = 0,
+    MLFMA_EINVAL = 1,  /* invalid argument (null pointer, bad size, NaN, ...) */
+    MLFMA_EDEPTH = 2,  /* tree deeper than max_levels or than 21 levels      */
+    MLFMA_ENOMEM = 3,  /* host or device allocation failed / over the limit  */
+    MLFMA_EDEVICE = 4, /* HIP runtime error (no device, launch failure, ...) */
+    MLFMA_ERANGE = 5   /* moved point left its box (mlfma_update_positions) */
+};
+
+enum mlfma_dtype { MLFMA_C64 = 0, MLFMA_C128 = 1 };
+
+/* parts of the matvec to evaluate (mlfma_matvec_ex) */
+enum mlfma_parts {
+    MLFMA_NEAR = 1, /* direct sum over near-field leaves                    */
+    MLFMA_FAR = 2,  /* C2M, M2M, M2L, L2L, L2O                               */
+    MLFMA_CONJ = 4  /* conjugate input and output: A^H v (adjoint)           */
+};
+
+/* mlfma_precompute_operators flags */
+enum mlfma_flags {
+    MLFMA_FP32 = 0,          /* FP32 interpolation / anterpolation GEMMs     */
+    MLFMA_BF16X3_INTERP = 1  /* interpolation GEMMs in BF16 split precision
+                                (hi*hi + hi*lo + lo*hi, FP32 accumulation)  */
+};
+
+typedef struct mlfma_tree_info {
+    int64_t n_points;
+    int32_t n_levels;    /* root = level 1, leaves = level n_levels          */
+    int32_t device;
+    double leaf_size;    /* side of a leaf box                               */
+    double root_size;    /* D0 = leaf_size * 2^(n_levels-1)                  */
+    double origin[3];    /* lowest corner of the root cube                   */
+    int64_t n_leaf_boxes;
+    int64_t n_near_pairs; /* sum over leaves of |near list| (incl. self)      */
+    int64_t n_p2p_pairs;  /* point pairs of the near field (incl. i = j)      */
+} mlfma_tree_info;
+
+typedef struct mlfma_level_info {
+    int32_t level;
+    int32_t L;          /* truncation order (0 if the level has no spectra)  */
+    int32_t ntheta;     /* L + 1 Gauss-Legendre nodes in cos(theta)          */
+    int32_t nphi;       /* 2L + 2 uniform samples in phi                     */
+    int64_t K;          /* ntheta * nphi samples per box                     */
+    int64_t nbox;       /* non-empty boxes at this level                     */
+    int64_t n_far;      /* far-field (observer, source) pairs at this level  */
+    int32_t n_types;    /* distinct translation offsets used                 */
+    int32_t pad;
+} mlfma_level_info;
+
+/*
+ * Build the octree (host only; no device call is made here).
+ * Sec. 3.1: n_levels is the smallest integer with
+ * leaf_size * 2^(n_levels-1) >= E, E the largest side of the points'
+ * bounding box; the root cube (side D0 = leaf_size * 2^(n_levels-1)) is
+ * centred on the bounding box.  A point's leaf box is
+ * floor((r - origin) / leaf_size) per axis, clamped into the cube; its box at
+ * level l is that index shifted right by n_levels - l; empty boxes are
+ * dropped; boxes and points are kept in Morton-Z order (ties by input index).
+ * Near field (leaf level): Chebyshev distance <= 1 (Sec. 2).  Far field at
+ * level l >= 3: not near, parents near (Sec. 2).
+ *
+ *   xyz        host, [n][3] doubles, caller order
+ *   n          >= 0 (n = 0 gives an empty tree; every matvec is a no-op)
+ *   leaf_size  > 0, finite
+ *   max_levels 1..21
+ *   device     HIP device ordinal used by mlfma_precompute_operators
+ *   out        receives the handle (owned by the caller; mlfma_destroy_tree)
+ * Errors: EINVAL (null pointer, n < 0, non-finite coordinate, bad leaf_size
+ *         or max_levels), EDEPTH, ENOMEM.
+ */
+int mlfma_build_tree(const double *xyz, int64_t n, double leaf_size,
+                     int max_levels, int device, mlfma_tree_t *out);
+
+/*
+ * Replace the point coordinates while keeping the tree's topology (used for
+ * finite-difference checks of position gradients).  Every point must stay in
+ * its leaf box (same floor index); otherwise ERANGE and nothing changes.
+ * Takes effect for operator handles created afterwards and, for existing
+ * handles, at their next call (the device copy is refreshed lazily).
+ */
+int mlfma_update_positions(mlfma_tree_t t, const double *xyz);
+
+/*
+ * Precompute everything a matvec needs, in FP64 on the host, and upload it
+ * (FP32 / complex64 tables) with the tree to the tree's device.  Per level
+ * l >= 3 the truncation order is
+ *     L = ceil(k d + 1.8 digits^(2/3) (k d)^(1/3)),  d = sqrt(3) a_l,
+ * samples are Gauss-Legendre in cos(theta) x 2L+2 uniform in phi, the
+ * translation operator of offset X is
+ *     T(khat) = sum_{l<=L} i^l (2l+1) h_l^(1)(k|X|) P_l(khat . X/|X|)
+ * (Sec. 3.2.3, translation operators, precomputed once), and the level-to-
+ * level maps are the exact band-limited interpolation (Sec. 2 related work,
+ * global interpolation; Sec. 3.2.2) and its weighted adjoint.
+ * Also allocates the workspace for up to max_rhs right-hand sides; matvec
+ * calls allocate nothing.
+ *
+ *   k       wavenumber > 0
+ *   digits  1..10 (3 = about three digits)
+ *   max_rhs 1..1024
+ *   flags   MLFMA_FP32 or MLFMA_BF16X3_INTERP
+ * Errors: EINVAL (k <= 0 or non-finite, digits, max_rhs, flags, a leaf box
+ *         with k sqrt(3) leaf_size < 1 while the tree has far-field levels --
+ *         the diagonal form is not accurate there), ENOMEM (device memory or
+ *         the limit of mlfma_set_device_memory_limit), EDEVICE.
+ * The ops handle keeps a reference to the tree (destroying the tree first is
+ * allowed).
+ */
+int mlfma_precompute_operators(mlfma_tree_t t, double k, int digits,
+                               int max_rhs, uint32_t flags, mlfma_ops_t *out);
+
+/*
+ * phi = A q (near + far), A_ij = exp(ik|r_i-r_j|)/|r_i-r_j|, A_ii = 0.
+ *   q, phi  device, [n][nrhs] complex in the caller's point order
+ *   nrhs    1..max_rhs
+ *   dtype   MLFMA_C64 or MLFMA_C128
+ *   stream  hipStream_t or NULL
+ * Errors: EINVAL (null handle/pointer with n > 0, nrhs, dtype), EDEVICE.
+ */
+int mlfma_matvec(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs,
+                 int dtype, void *stream);
+
+/*
+ * psi = A^H v = conj(A conj(v)) -- the conjugate-wavenumber MLFMA.  The
+ * discrete operator is symmetric (antipodal sample grids, anterpolation the
+ * weighted adjoint of interpolation), so this is its exact adjoint up to
+ * rounding.  Same arguments and errors as mlfma_matvec.
+ */
+int mlfma_matvec_adjoint(mlfma_ops_t ops, const void *v, void *psi,
+                         int64_t nrhs, int dtype, void *stream);
+
+/*
+ * As mlfma_matvec, evaluating only the parts in `parts` (MLFMA_NEAR,
+ * MLFMA_FAR, optionally MLFMA_CONJ).  parts must contain NEAR or FAR.
+ */
+int mlfma_matvec_ex(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs,
+                    int dtype, uint32_t parts, void *stream);
+
+/*
+ * Gradient of the potential at every point with respect to that point's
+ * position, self term excluded:
+ *     grad[i][c][a] = sum_{j != i} q_j[c] d/dr_i,a G(r_i - r_j),
+ *     grad G(r) = G(r) (ik - 1/|r|) r/|r|.
+ * Near part direct; far part = L2O with the extra factor ik khat.
+ *   q     device [n][nrhs] complex;  grad  device [n][nrhs][3] complex
+ * With parts = MLFMA_CONJ (others ignored) evaluates conj of the field of
+ * conj(q).  Same errors as mlfma_matvec.
+ */
+int mlfma_field(mlfma_ops_t ops, const void *q, void *grad, int64_t nrhs,
+                int dtype, uint32_t parts, void *stream);
+
+/* NULL is a no-op.  Wait for outstanding work on the handle's streams first. */
+void mlfma_destroy_ops(mlfma_ops_t ops);
+void mlfma_destroy_tree(mlfma_tree_t t);
+
+/* Host-side queries (no device call). */
+int mlfma_tree_info_get(mlfma_tree_t t, mlfma_tree_info *out);
+/* perm[s] = caller index of the point at Morton-sorted position s; host [n] */
+int mlfma_tree_permutation(mlfma_tree_t t, int64_t *perm);
+/* box count (*nbox), integer box coordinates [nbox][3] and parent index
+ * [nbox] (-1 at level 1) of level `level` (1..n_levels), in the library's
+ * box order; coords and parent may be NULL to query the count only */
+int mlfma_tree_level(mlfma_tree_t t, int level, int64_t *nbox,
+                     int32_t *coords, int32_t *parent);
+/* far-field pairs of level `level` (3..n_levels): observer, source and the
+ * offset code (dx+3)*49+(dy+3)*7+(dz+3) of c_obs - c_src; *count receives
+ * the pair count; arrays may be NULL to query the count only */
+int mlfma_tree_far_list(mlfma_tree_t t, int level, int64_t *count,
+                        int32_t *obs, int32_t *src, int32_t *code);
+/* near lists of the leaves in CSR form: start [nleaf+1], idx [n_near_pairs] */
+int mlfma_tree_near_list(mlfma_tree_t t, int64_t *start, int32_t *idx);
+/* info for levels 1..n_levels into out[0..n_levels-1] (max entries given) */
+int mlfma_ops_info(mlfma_ops_t ops, mlfma_level_info *out, int max_entries);
+
+/*
+ * Diagnostics: copy the spectra the last call left in the workspace.
+ *   which 0 = multipole expansions, 1 = local expansions (after L2L)
+ *   dst   device buffer of nbox * nrhs * K complex64, layout [box][rhs][K]
+ *         with samples [theta][phi], theta ascending, phi_j = 2 pi j / nphi
+ */
+int mlfma_copy_spectra(mlfma_ops_t ops, int level, int which, int64_t nrhs,
+                       void *dst, void *stream);
+
+/*
+ * Kernel ids for mlfma_profile_*: one id per kernel of the matvec.
+ */
+enum mlfma_kernel_id {
+    MLFMA_K_GATHER = 0,    /* caller order -> Morton order (+ conj, dtype)   */
+    MLFMA_K_P2P = 1,       /* near field                                     */
+    MLFMA_K_C2M = 2,       /* leaf signatures                                */
+    MLFMA_K_INTERP_S1 = 3, /* M2M: phi DFT on the child grid                 */
+    MLFMA_K_INTERP_S2 = 4, /* M2M: per-order theta maps                      */
+    MLFMA_K_INTERP_S3 = 5, /* M2M: phi synthesis + shift + aggregation       */
+    MLFMA_K_M2L = 6,       /* translation over far lists                     */
+    MLFMA_K_ANTERP_S1 = 7, /* L2L: shift + phi DFT on the parent grid        */
+    MLFMA_K_ANTERP_S2 = 8, /* L2L: per-order theta maps                      */
+    MLFMA_K_ANTERP_S3 = 9, /* L2L: phi synthesis + add                       */
+    MLFMA_K_L2O = 10,      /* leaf evaluation + near + scatter               */
+    MLFMA_K_COUNT = 11
+};
+
+/*
+ * Diagnostics: time kernel launches of this handle with HIP events recorded
+ * on the launch stream.  Every launch whose id bit is set in kernel_mask is
+ * bracketed by an event pair, for at most max_launches launches (the events
+ * are created here).  mlfma_profile_end waits for the events, writes the
+ * summed milliseconds and launch counts per id into ms[MLFMA_K_COUNT] and
+ * launches[MLFMA_K_COUNT], and stops recording.
+ */
+int mlfma_profile_begin(mlfma_ops_t ops, uint32_t kernel_mask,
+                        int64_t max_launches);
+int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
+
+/*
+ * Cap on the device bytes mlfma_precompute_operators may allocate (0 = no
+ * cap).  The check happens before any device call, so exceeding it returns
+ * ENOMEM without touching the GPU.  Process-wide.
+ */
+void mlfma_set_device_memory_limit(int64_t bytes);
+
+const char *mlfma_status_string(int status);
+const char *mlfma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLFMA_H */

@@ -1,4 +1,4 @@
-"""Plain FP64 MLFMA for phi_i = sum_{j != i} q_j exp(ik|r_i - r_j|)/|r_i - r_j|
+r"""Plain FP64 MLFMA for phi_i = sum_{j != i} q_j exp(ik|r_i - r_j|)/|r_i - r_j|
 (oracle; test infrastructure only -- the product path never imports this).
 
 Follows the paper's rubric step by step (Sec. 2, the five-stage list; Sec.

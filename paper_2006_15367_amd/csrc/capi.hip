@@ -1,0 +1,648 @@
+// C ABI of the MLFMA library: handles, uploads, and the order of the
+// kernels of one matvec (paper Sec. 2 five-stage list: C2M, M2M, M2L, L2L,
+// L2O, plus the leaf-level near field).
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace mlfma {
+const char *last_error_text();
+}
+
+using namespace mlfma;
+
+namespace {
+
+std::atomic<int64_t> g_mem_limit{0};
+
+struct DevLevel {
+    int64_t nbox = 0;
+    int L = 0, nth = 0, nph = 0;
+    int64_t K = 0;
+    int ntypes = 0;
+    float4 *khat_w = nullptr;
+    float2 *T = nullptr;
+    int32_t *far_start = nullptr, *far_src = nullptr;
+    int16_t *far_type = nullptr;
+    int64_t n_far = 0;
+    int32_t *parent = nullptr;       // into level-1
+    uint8_t *oct = nullptr;          // octant of the box inside its parent
+    int32_t *child_start = nullptr;  // into level+1
+    float2 *S = nullptr, *Lloc = nullptr;  // [nbox][R][K]
+    int Lc = 0, Mc = 0;
+    float2 *shift = nullptr;
+    float *iF = nullptr, *iA = nullptr, *iG = nullptr;
+    float *aF = nullptr, *aB = nullptr, *aG = nullptr;
+};
+
+}  // namespace
+
+struct mlfma_ops_s {
+    Tree *tree = nullptr;
+    double k = 0;
+    int digits = 0, max_rhs = 0;
+    uint32_t flags = 0;
+    int device = 0;
+    int64_t n = 0;
+    int n_lev = 0;
+    std::vector<LevelTables> tab;  // host tables (kept for info queries)
+    std::vector<DevLevel> lev;
+    float4 *pts = nullptr;
+    int32_t *perm = nullptr, *pt_leaf = nullptr, *pt_start = nullptr;
+    int32_t *near_start = nullptr, *near_idx = nullptr, *leaf_coord = nullptr;
+    float2 *qs = nullptr, *near = nullptr;
+    float2 *X1 = nullptr, *X2 = nullptr;
+    int64_t scratch_elems = 0;
+    uint64_t pos_version = 0;
+    std::vector<void *> allocs;
+    int64_t last_R = 0;
+    // launch timing (diagnostics)
+    uint32_t prof_mask = 0;
+    int64_t prof_cap = 0, prof_used = 0;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_id;
+};
+
+#define CK(x)                                                   \
+    do {                                                        \
+        hipError_t _e = (x);                                    \
+        if (_e != hipSuccess) return check_hip(_e, #x);         \
+    } while (0)
+
+// launch `x` (a dev:: launcher) as kernel `id`, bracketed by profiling
+// events when that id is being timed
+#define LAUNCH(id, x)                                           \
+    do {                                                        \
+        const bool _p = prof_start(o, (id), s);                 \
+        hipError_t _e = (x);                                    \
+        if (_p) prof_stop(o, s);                                \
+        if (_e != hipSuccess) return check_hip(_e, #x);         \
+    } while (0)
+
+namespace {
+
+// ---------------------------------------------------------------- memory --
+struct Planner {
+    int64_t bytes = 0;
+    void add(int64_t b) { bytes += (b + 255) / 256 * 256; }
+};
+
+bool prof_start(mlfma_ops_s *o, int id, hipStream_t s)
+{
+    if (!(o->prof_mask & (1u << id)) || o->prof_used >= o->prof_cap) return false;
+    if (hipEventRecord(o->prof_ev[2 * o->prof_used], s) != hipSuccess) return false;
+    o->prof_id[o->prof_used] = id;
+    return true;
+}
+
+void prof_stop(mlfma_ops_s *o, hipStream_t s)
+{
+    (void)hipEventRecord(o->prof_ev[2 * o->prof_used + 1], s);
+    ++o->prof_used;
+}
+
+void prof_release(mlfma_ops_s *o)
+{
+    for (hipEvent_t e : o->prof_ev) (void)hipEventDestroy(e);
+    o->prof_ev.clear();
+    o->prof_id.clear();
+    o->prof_mask = 0;
+    o->prof_cap = o->prof_used = 0;
+}
+
+template <typename T>
+int dalloc(mlfma_ops_s *o, T **p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) return MLFMA_OK;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? MLFMA_ENOMEM : MLFMA_EDEVICE,
+                    "hipMalloc(%lld bytes): %s", (long long)(count * sizeof(T)),
+                    hipGetErrorString(e));
+    }
+    o->allocs.push_back(q);
+    *p = (T *)q;
+    return MLFMA_OK;
+}
+
+template <typename T>
+int upload(mlfma_ops_s *o, T **p, const T *src, int64_t count)
+{
+    int rc = dalloc(o, p, count);
+    if (rc || count <= 0) return rc;
+    hipError_t e = hipMemcpy(*p, src, (size_t)count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(MLFMA_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    return MLFMA_OK;
+}
+
+void free_ops(mlfma_ops_s *o)
+{
+    if (!o) return;
+    prof_release(o);
+    if (!o->allocs.empty()) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess) {
+            (void)hipSetDevice(o->device);
+            for (void *p : o->allocs) (void)hipFree(p);
+            (void)hipSetDevice(cur);
+        }
+    }
+    release_tree(o->tree);
+    delete o;
+}
+
+// leaf-local FP32 offsets of the sorted points
+std::vector<float4> point_offsets(const Tree &t)
+{
+    std::vector<float4> p(t.n);
+    const HostLevel &leaf = t.lev[t.n_lev];
+    for (int64_t s = 0; s < t.n; ++s) {
+        const int64_t i = t.perm[s];
+        const int32_t *c = &leaf.coord[3 * t.pt_leaf[s]];
+        float v[3];
+        for (int a = 0; a < 3; ++a) {
+            const double centre = t.origin[a] + (c[a] + 0.5) * t.leaf;
+            v[a] = (float)(t.xyz[3 * i + a] - centre);
+        }
+        p[s] = make_float4(v[0], v[1], v[2], 0.f);
+    }
+    return p;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return MLFMA_OK;
+    return fail(MLFMA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int refresh_positions(mlfma_ops_s *o)
+{
+    if (o->pos_version == o->tree->pos_version) return MLFMA_OK;
+    std::vector<float4> p = point_offsets(*o->tree);
+    hipError_t e = hipMemcpy(o->pts, p.data(), p.size() * sizeof(float4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return check_hip(e, "position upload");
+    o->pos_version = o->tree->pos_version;
+    return MLFMA_OK;
+}
+
+// ---------------------------------------------------------------- matvec --
+// The far field: C2M, M2M up the tree, M2L per level, L2L down the tree.
+// Leaves the leaf-level local expansions in lev[n_lev].Lloc.
+int run_far(mlfma_ops_s *o, int R, hipStream_t s)
+{
+    const int nl = o->n_lev;
+    DevLevel &leaf = o->lev[nl];
+    const float kw = (float)o->k;
+    LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
+    for (int l = nl - 1; l >= 3; --l) {
+        DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+        const int M = P.Mc;
+        LAUNCH(MLFMA_K_INTERP_S1, dev::dft_rows(C.S, C.nbox * R * C.nth, C.nph, P.iF, M, o->X1, s));
+        LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s));
+        LAUNCH(MLFMA_K_INTERP_S3, dev::interp_s3(P.nbox, R, P.nth, P.nph, M, P.child_start, C.oct, o->X2, P.iG,
+                          P.shift, P.S, s));
+    }
+    for (int l = 3; l <= nl; ++l) {
+        DevLevel &D = o->lev[l];
+        LAUNCH(MLFMA_K_M2L, dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s));
+    }
+    for (int l = 3; l < nl; ++l) {
+        DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+        const int M = P.Mc;
+        LAUNCH(MLFMA_K_ANTERP_S1, dev::anterp_s1(P.Lloc, C.parent, C.oct, C.nbox, R, P.nth, P.nph, P.shift, P.aF, M,
+                          o->X1, s));
+        LAUNCH(MLFMA_K_ANTERP_S2, dev::theta_map(o->X1, C.nbox * R, P.nth, M, P.aB, C.nth, o->X2, s));
+        LAUNCH(MLFMA_K_ANTERP_S3, dev::anterp_s3(C.nbox, R, C.nth, C.nph, M, o->X2, P.aG, C.Lloc, s));
+    }
+    return MLFMA_OK;
+}
+
+int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
+              uint32_t parts, int field, hipStream_t s)
+{
+    if (!o) return fail(MLFMA_EINVAL, "matvec: ops handle is NULL");
+    if (nrhs < 1 || nrhs > o->max_rhs)
+        return fail(MLFMA_EINVAL, "matvec: nrhs=%lld outside 1..%d", (long long)nrhs, o->max_rhs);
+    if (dtype != MLFMA_C64 && dtype != MLFMA_C128)
+        return fail(MLFMA_EINVAL, "matvec: unknown dtype %d", dtype);
+    if (!field && !(parts & (MLFMA_NEAR | MLFMA_FAR)))
+        return fail(MLFMA_EINVAL, "matvec: parts must include MLFMA_NEAR or MLFMA_FAR");
+    if (parts & ~7u) return fail(MLFMA_EINVAL, "matvec: unknown parts bits");
+    if (field) parts = (parts & MLFMA_CONJ) | MLFMA_NEAR | MLFMA_FAR;
+    if (o->n == 0) return MLFMA_OK;
+    if (!q || !out) return fail(MLFMA_EINVAL, "matvec: null buffer");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(MLFMA_EDEVICE, "hipGetDevice failed");
+    if (cur != o->device && hipSetDevice(o->device) != hipSuccess)
+        return fail(MLFMA_EDEVICE, "hipSetDevice(%d) failed", o->device);
+    int rc = refresh_positions(o);
+    const int R = (int)nrhs;
+    const int conj = (parts & MLFMA_CONJ) ? 1 : 0;
+    const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
+    if (rc == MLFMA_OK) {
+        rc = [&]() -> int {
+            LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, conj, o->qs, s));
+            const int64_t nnear = o->n * R * (field ? 3 : 1);
+            if (parts & MLFMA_NEAR)
+                LAUNCH(MLFMA_K_P2P, dev::p2p(o->pts, o->pt_leaf, o->pt_start, o->near_start, o->near_idx,
+                            o->leaf_coord, (float)o->tree->leaf, (float)o->k, o->qs, o->n, R,
+                            field, o->near, s));
+            else
+                LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
+            if (far) {
+                int r2 = run_far(o, R, s);
+                if (r2) return r2;
+            }
+            DevLevel &leaf = o->lev[o->n_lev];
+            LAUNCH(MLFMA_K_L2O, dev::l2o_scatter(o->pts, o->pt_leaf, o->perm, far ? leaf.khat_w : nullptr,
+                                far ? leaf.K : 0, (float)o->k, far ? leaf.Lloc : nullptr,
+                                o->near, o->n, R, field, far ? 1 : 0, conj, dtype, out, s));
+            return MLFMA_OK;
+        }();
+    }
+    o->last_R = R;
+    if (cur != o->device) (void)hipSetDevice(cur);
+    return rc;
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+extern "C" {
+
+int mlfma_build_tree(const double *xyz, int64_t n, double leaf_size, int max_levels, int device,
+                     mlfma_tree_t *out)
+{
+    if (!out) return fail(MLFMA_EINVAL, "build_tree: out is NULL");
+    Tree *t = nullptr;
+    int rc = build_tree(xyz, n, leaf_size, max_levels, device, &t);
+    if (rc) return rc;
+    // mlfma_tree_s adds no members: reinterpret the Tree as the opaque handle
+    *out = reinterpret_cast<mlfma_tree_t>(t);
+    return MLFMA_OK;
+}
+
+int mlfma_update_positions(mlfma_tree_t t, const double *xyz)
+{
+    return update_positions(reinterpret_cast<Tree *>(t), xyz);
+}
+
+void mlfma_set_device_memory_limit(int64_t bytes) { g_mem_limit.store(bytes < 0 ? 0 : bytes); }
+
+int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rhs,
+                               uint32_t flags, mlfma_ops_t *out)
+{
+    if (!out) return fail(MLFMA_EINVAL, "precompute: out is NULL");
+    *out = nullptr;
+    Tree *t = reinterpret_cast<Tree *>(th);
+    if (!t) return fail(MLFMA_EINVAL, "precompute: tree is NULL");
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(MLFMA_EINVAL, "precompute: k must be > 0");
+    if (digits < 1 || digits > 10) return fail(MLFMA_EINVAL, "precompute: digits outside 1..10");
+    if (max_rhs < 1 || max_rhs > 1024)
+        return fail(MLFMA_EINVAL, "precompute: max_rhs outside 1..1024");
+    if (flags & ~(uint32_t)MLFMA_BF16X3_INTERP)
+        return fail(MLFMA_EINVAL, "precompute: unknown flags");
+    if (t->n_lev >= 3 && k * std::sqrt(3.0) * t->leaf < 1.0)
+        return fail(MLFMA_EINVAL,
+                    "precompute: leaf boxes too small for the diagonal form (k sqrt(3) a = %g < 1)",
+                    k * std::sqrt(3.0) * t->leaf);
+
+    mlfma_ops_s *o = new (std::nothrow) mlfma_ops_s();
+    if (!o) return fail(MLFMA_ENOMEM, "precompute: out of host memory");
+    o->tree = t;
+    ++t->refcount;
+    o->k = k;
+    o->digits = digits;
+    o->max_rhs = max_rhs;
+    o->flags = flags;
+    o->device = t->device;
+    o->n = t->n;
+    o->n_lev = t->n_lev;
+    int rc = build_level_tables(*t, k, digits, o->tab);
+    if (rc) {
+        free_ops(o);
+        return rc;
+    }
+    const int nl = t->n_lev;
+    const int64_t R = max_rhs;
+    const int64_t nleaf = t->lev[nl].nbox;
+    // ---- plan the device bytes before touching the device
+    Planner pl;
+    pl.add(t->n * 16);                 // pts
+    pl.add(t->n * 4 * 2);              // perm, pt_leaf
+    pl.add((nleaf + 1) * 4 * 2);       // pt_start, near_start
+    pl.add((int64_t)t->near_idx.size() * 4);
+    pl.add(nleaf * 12);
+    pl.add(t->n * R * 8);              // qs
+    pl.add(t->n * R * 8 * 3);          // near (3 components for the field)
+    int64_t scratch = 0;
+    if (nl >= 3) {
+        for (int l = 3; l <= nl; ++l) {
+            const LevelTables &T = o->tab[l];
+            const HostLevel &H = t->lev[l];
+            pl.add(T.K * 16);
+            pl.add((int64_t)T.ntypes * T.K * 8);
+            pl.add((H.nbox + 1) * 4);
+            pl.add((int64_t)H.far_src.size() * 6);
+            pl.add(H.nbox * 5);
+            pl.add((H.nbox + 1) * 4);
+            pl.add(H.nbox * R * T.K * 8 * 2);
+            if (l < nl) {
+                const LevelTables &C = o->tab[l + 1];
+                pl.add(8 * T.K * 8);
+                pl.add(((int64_t)T.iF.size() + T.iA.size() + T.iG.size() + T.aF.size() +
+                        T.aB.size() + T.aG.size()) * 4);
+                const int64_t e = t->lev[l + 1].nbox * R * std::max(C.nth, T.nth) * T.Mc;
+                scratch = std::max(scratch, e);
+            }
+        }
+        pl.add(scratch * 8 * 2);
+    }
+    const int64_t lim = g_mem_limit.load();
+    if (lim > 0 && pl.bytes > lim) {
+        rc = fail(MLFMA_ENOMEM, "precompute: needs %lld device bytes, limit is %lld",
+                  (long long)pl.bytes, (long long)lim);
+        free_ops(o);
+        return rc;
+    }
+    // ---- device
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(o->device) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = fail(MLFMA_EDEVICE, "precompute: cannot use HIP device %d", o->device);
+        free_ops(o);
+        return rc;
+    }
+    rc = [&]() -> int {
+        int r;
+        std::vector<float4> p = point_offsets(*t);
+        if ((r = upload(o, &o->pts, p.data(), t->n))) return r;
+        std::vector<int32_t> v32(t->perm.begin(), t->perm.end());
+        if ((r = upload(o, &o->perm, v32.data(), t->n))) return r;
+        if ((r = upload(o, &o->pt_leaf, t->pt_leaf.data(), t->n))) return r;
+        v32.assign(t->pt_start.begin(), t->pt_start.end());
+        if ((r = upload(o, &o->pt_start, v32.data(), (int64_t)v32.size()))) return r;
+        v32.assign(t->near_start.begin(), t->near_start.end());
+        if ((r = upload(o, &o->near_start, v32.data(), (int64_t)v32.size()))) return r;
+        if ((r = upload(o, &o->near_idx, t->near_idx.data(), (int64_t)t->near_idx.size()))) return r;
+        if ((r = upload(o, &o->leaf_coord, t->lev[nl].coord.data(), 3 * nleaf))) return r;
+        if ((r = dalloc(o, &o->qs, t->n * R))) return r;
+        if ((r = dalloc(o, &o->near, t->n * R * 3))) return r;
+        o->lev.resize(nl + 1);
+        for (int l = 1; l <= nl; ++l) o->lev[l].nbox = t->lev[l].nbox;
+        if (nl < 3) return MLFMA_OK;
+        for (int l = 3; l <= nl; ++l) {
+            DevLevel &D = o->lev[l];
+            const LevelTables &T = o->tab[l];
+            const HostLevel &H = t->lev[l];
+            D.L = T.L;
+            D.nth = T.nth;
+            D.nph = T.nph;
+            D.K = T.K;
+            D.ntypes = T.ntypes;
+            D.n_far = (int64_t)H.far_src.size();
+            if ((r = upload(o, &D.khat_w, (const float4 *)T.khat_w.data(), T.K))) return r;
+            if ((r = upload(o, &D.T, (const float2 *)T.T.data(), (int64_t)T.ntypes * T.K))) return r;
+            if ((r = upload(o, &D.far_start, H.far_start.data(), H.nbox + 1))) return r;
+            if ((r = upload(o, &D.far_src, H.far_src.data(), D.n_far))) return r;
+            if ((r = upload(o, &D.far_type, T.far_type.data(), D.n_far))) return r;
+            if ((r = upload(o, &D.parent, H.parent.data(), H.nbox))) return r;
+            std::vector<uint8_t> oc(H.nbox);
+            for (int64_t b = 0; b < H.nbox; ++b)
+                oc[b] = (uint8_t)(((H.coord[3 * b] & 1) << 2) | ((H.coord[3 * b + 1] & 1) << 1) |
+                                  (H.coord[3 * b + 2] & 1));
+            if ((r = upload(o, &D.oct, oc.data(), H.nbox))) return r;
+            if ((r = dalloc(o, &D.S, H.nbox * R * T.K))) return r;
+            if ((r = dalloc(o, &D.Lloc, H.nbox * R * T.K))) return r;
+            if (l < nl) {
+                if ((r = upload(o, &D.child_start, H.child_start.data(), H.nbox + 1))) return r;
+                D.Lc = T.Lc;
+                D.Mc = T.Mc;
+                if ((r = upload(o, &D.shift, (const float2 *)T.shift.data(), 8 * T.K))) return r;
+                if ((r = upload(o, &D.iF, T.iF.data(), (int64_t)T.iF.size()))) return r;
+                if ((r = upload(o, &D.iA, T.iA.data(), (int64_t)T.iA.size()))) return r;
+                if ((r = upload(o, &D.iG, T.iG.data(), (int64_t)T.iG.size()))) return r;
+                if ((r = upload(o, &D.aF, T.aF.data(), (int64_t)T.aF.size()))) return r;
+                if ((r = upload(o, &D.aB, T.aB.data(), (int64_t)T.aB.size()))) return r;
+                if ((r = upload(o, &D.aG, T.aG.data(), (int64_t)T.aG.size()))) return r;
+            }
+        }
+        o->scratch_elems = scratch;
+        if ((r = dalloc(o, &o->X1, scratch))) return r;
+        if ((r = dalloc(o, &o->X2, scratch))) return r;
+        return MLFMA_OK;
+    }();
+    (void)hipSetDevice(cur);
+    if (rc) {
+        free_ops(o);
+        return rc;
+    }
+    o->pos_version = t->pos_version;
+    *out = o;
+    return MLFMA_OK;
+}
+
+int mlfma_matvec(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs, int dtype, void *stream)
+{
+    return do_matvec(ops, q, phi, nrhs, dtype, MLFMA_NEAR | MLFMA_FAR, 0, (hipStream_t)stream);
+}
+
+int mlfma_matvec_adjoint(mlfma_ops_t ops, const void *v, void *psi, int64_t nrhs, int dtype,
+                         void *stream)
+{
+    return do_matvec(ops, v, psi, nrhs, dtype, MLFMA_NEAR | MLFMA_FAR | MLFMA_CONJ, 0,
+                     (hipStream_t)stream);
+}
+
+int mlfma_matvec_ex(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs, int dtype,
+                    uint32_t parts, void *stream)
+{
+    return do_matvec(ops, q, phi, nrhs, dtype, parts, 0, (hipStream_t)stream);
+}
+
+int mlfma_field(mlfma_ops_t ops, const void *q, void *grad, int64_t nrhs, int dtype,
+                uint32_t parts, void *stream)
+{
+    return do_matvec(ops, q, grad, nrhs, dtype, parts, 1, (hipStream_t)stream);
+}
+
+void mlfma_destroy_ops(mlfma_ops_t ops) { free_ops(ops); }
+
+void mlfma_destroy_tree(mlfma_tree_t t) { release_tree(reinterpret_cast<Tree *>(t)); }
+
+int mlfma_tree_info_get(mlfma_tree_t th, mlfma_tree_info *out)
+{
+    Tree *t = reinterpret_cast<Tree *>(th);
+    if (!t || !out) return fail(MLFMA_EINVAL, "tree_info: null argument");
+    std::memset(out, 0, sizeof *out);
+    out->n_points = t->n;
+    out->n_levels = t->n_lev;
+    out->device = t->device;
+    out->leaf_size = t->leaf;
+    out->root_size = t->D0;
+    for (int a = 0; a < 3; ++a) out->origin[a] = t->origin[a];
+    out->n_leaf_boxes = t->lev[t->n_lev].nbox;
+    out->n_near_pairs = (int64_t)t->near_idx.size();
+    out->n_p2p_pairs = t->n_p2p_pairs;
+    return MLFMA_OK;
+}
+
+int mlfma_tree_permutation(mlfma_tree_t th, int64_t *perm)
+{
+    Tree *t = reinterpret_cast<Tree *>(th);
+    if (!t || (!perm && t->n > 0)) return fail(MLFMA_EINVAL, "tree_permutation: null argument");
+    std::memcpy(perm, t->perm.data(), t->perm.size() * sizeof(int64_t));
+    return MLFMA_OK;
+}
+
+int mlfma_tree_level(mlfma_tree_t th, int level, int64_t *nbox, int32_t *coords,
+                     int32_t *parent)
+{
+    Tree *t = reinterpret_cast<Tree *>(th);
+    if (!t || !nbox) return fail(MLFMA_EINVAL, "tree_level: null argument");
+    if (level < 1 || level > t->n_lev) return fail(MLFMA_EINVAL, "tree_level: bad level %d", level);
+    const HostLevel &L = t->lev[level];
+    *nbox = L.nbox;
+    if (coords) std::memcpy(coords, L.coord.data(), L.coord.size() * sizeof(int32_t));
+    if (parent) std::memcpy(parent, L.parent.data(), L.parent.size() * sizeof(int32_t));
+    return MLFMA_OK;
+}
+
+int mlfma_tree_far_list(mlfma_tree_t th, int level, int64_t *count, int32_t *obs, int32_t *src,
+                        int32_t *code)
+{
+    Tree *t = reinterpret_cast<Tree *>(th);
+    if (!t || !count) return fail(MLFMA_EINVAL, "tree_far_list: null argument");
+    if (level < 3 || level > t->n_lev)
+        return fail(MLFMA_EINVAL, "tree_far_list: bad level %d", level);
+    const HostLevel &L = t->lev[level];
+    *count = (int64_t)L.far_src.size();
+    for (int64_t b = 0; b < L.nbox; ++b)
+        for (int32_t e = L.far_start[b]; e < L.far_start[b + 1]; ++e) {
+            if (obs) obs[e] = (int32_t)b;
+            if (src) src[e] = L.far_src[e];
+            if (code) code[e] = L.far_code[e];
+        }
+    return MLFMA_OK;
+}
+
+int mlfma_tree_near_list(mlfma_tree_t th, int64_t *start, int32_t *idx)
+{
+    Tree *t = reinterpret_cast<Tree *>(th);
+    if (!t) return fail(MLFMA_EINVAL, "tree_near_list: tree is NULL");
+    if (start) std::memcpy(start, t->near_start.data(), t->near_start.size() * sizeof(int64_t));
+    if (idx) std::memcpy(idx, t->near_idx.data(), t->near_idx.size() * sizeof(int32_t));
+    return MLFMA_OK;
+}
+
+int mlfma_ops_info(mlfma_ops_t o, mlfma_level_info *out, int max_entries)
+{
+    if (!o || !out) return fail(MLFMA_EINVAL, "ops_info: null argument");
+    const Tree *t = o->tree;
+    for (int l = 1; l <= t->n_lev && l <= max_entries; ++l) {
+        mlfma_level_info &I = out[l - 1];
+        std::memset(&I, 0, sizeof I);
+        I.level = l;
+        I.nbox = t->lev[l].nbox;
+        if (l >= 3) {
+            const LevelTables &T = o->tab[l];
+            I.L = T.L;
+            I.ntheta = T.nth;
+            I.nphi = T.nph;
+            I.K = T.K;
+            I.n_far = (int64_t)t->lev[l].far_src.size();
+            I.n_types = T.ntypes;
+        }
+    }
+    return MLFMA_OK;
+}
+
+int mlfma_copy_spectra(mlfma_ops_t o, int level, int which, int64_t nrhs, void *dst, void *stream)
+{
+    if (!o || !dst) return fail(MLFMA_EINVAL, "copy_spectra: null argument");
+    if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "copy_spectra: bad level");
+    if (nrhs < 1 || nrhs > o->max_rhs) return fail(MLFMA_EINVAL, "copy_spectra: bad nrhs");
+    const DevLevel &D = o->lev[level];
+    const float2 *src = which == 0 ? D.S : D.Lloc;
+    hipError_t e = hipMemcpyAsync(dst, src, (size_t)(D.nbox * nrhs * D.K) * sizeof(float2),
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return check_hip(e, "copy_spectra");
+}
+
+int mlfma_profile_begin(mlfma_ops_t o, uint32_t kernel_mask, int64_t max_launches)
+{
+    if (!o) return fail(MLFMA_EINVAL, "profile_begin: ops is NULL");
+    if (max_launches < 0 || max_launches > (1 << 20))
+        return fail(MLFMA_EINVAL, "profile_begin: max_launches outside 0..2^20");
+    prof_release(o);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(MLFMA_EDEVICE, "hipGetDevice failed");
+    (void)hipSetDevice(o->device);
+    o->prof_ev.resize(2 * max_launches);
+    int rc = MLFMA_OK;
+    for (int64_t i = 0; i < 2 * max_launches; ++i)
+        if (hipEventCreate(&o->prof_ev[i]) != hipSuccess) {
+            o->prof_ev.resize(i);
+            rc = fail(MLFMA_EDEVICE, "profile_begin: hipEventCreate failed");
+            break;
+        }
+    (void)hipSetDevice(cur);
+    if (rc) {
+        prof_release(o);
+        return rc;
+    }
+    o->prof_id.assign(max_launches, -1);
+    o->prof_cap = max_launches;
+    o->prof_used = 0;
+    o->prof_mask = kernel_mask;
+    return MLFMA_OK;
+}
+
+int mlfma_profile_end(mlfma_ops_t o, double *ms, int64_t *launches)
+{
+    if (!o || !ms || !launches) return fail(MLFMA_EINVAL, "profile_end: null argument");
+    for (int i = 0; i < MLFMA_K_COUNT; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    int rc = MLFMA_OK;
+    for (int64_t u = 0; u < o->prof_used; ++u) {
+        float t = 0.f;
+        if (hipEventSynchronize(o->prof_ev[2 * u + 1]) != hipSuccess ||
+            hipEventElapsedTime(&t, o->prof_ev[2 * u], o->prof_ev[2 * u + 1]) != hipSuccess) {
+            rc = fail(MLFMA_EDEVICE, "profile_end: event query failed");
+            break;
+        }
+        ms[o->prof_id[u]] += t;
+        launches[o->prof_id[u]] += 1;
+    }
+    prof_release(o);
+    return rc;
+}
+
+const char *mlfma_status_string(int status)
+{
+    switch (status) {
+    case MLFMA_OK: return "MLFMA_OK";
+    case MLFMA_EINVAL: return "MLFMA_EINVAL: invalid argument";
+    case MLFMA_EDEPTH: return "MLFMA_EDEPTH: tree too deep";
+    case MLFMA_ENOMEM: return "MLFMA_ENOMEM: out of memory";
+    case MLFMA_EDEVICE: return "MLFMA_EDEVICE: HIP device error";
+    case MLFMA_ERANGE: return "MLFMA_ERANGE: point left its box";
+    default: return "unknown status";
+    }
+}
+
+const char *mlfma_last_error(void) { return last_error_text(); }
+
+}  // extern "C"

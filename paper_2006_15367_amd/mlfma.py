@@ -1,0 +1,319 @@
+"""Python binding of the MLFMA C ABI (``include/mlfma.h``): argument
+marshalling only.  Every step of the matvec runs in the HIP kernels of
+``libmlfma.so``; PyTorch provides device memory and the current stream.
+
+There is no fallback: if the library is missing or fails to load, every
+call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmlfma.so")
+
+OK, EINVAL, EDEPTH, ENOMEM, EDEVICE, ERANGE = range(6)
+C64, C128 = 0, 1
+NEAR, FAR, CONJ = 1, 2, 4
+FP32, BF16X3_INTERP = 0, 1
+KERNELS = ["gather", "p2p", "c2m", "interp_s1", "interp_s2", "interp_s3", "m2l",
+           "anterp_s1", "anterp_s2", "anterp_s3", "l2o"]
+
+_lib = None
+
+
+class MlfmaError(RuntimeError):
+    def __init__(self, status, where):
+        lib = _load()
+        msg = lib.mlfma_last_error().decode(errors="replace")
+        name = lib.mlfma_status_string(status).decode(errors="replace")
+        super().__init__("%s failed: %s (%s)" % (where, name, msg))
+        self.status = status
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("leaf_size", ctypes.c_double),
+                ("root_size", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("n_leaf_boxes", ctypes.c_int64), ("n_near_pairs", ctypes.c_int64),
+                ("n_p2p_pairs", ctypes.c_int64)]
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("ntheta", ctypes.c_int32), ("nphi", ctypes.c_int32),
+                ("K", ctypes.c_int64), ("nbox", ctypes.c_int64),
+                ("n_far", ctypes.c_int64), ("n_types", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+EXPORTS = {
+    "mlfma_build_tree": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                          ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "mlfma_update_positions": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_precompute_operators": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_uint32,
+                                    ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "mlfma_matvec": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                      ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_matvec_adjoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_matvec_ex": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                         ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_field": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                     ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_destroy_ops": ([ctypes.c_void_p], None),
+    "mlfma_destroy_tree": ([ctypes.c_void_p], None),
+    "mlfma_tree_info_get": ([ctypes.c_void_p, ctypes.POINTER(TreeInfo)], ctypes.c_int),
+    "mlfma_tree_permutation": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_tree_level": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_tree_far_list": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_tree_near_list": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                             ctypes.c_int),
+    "mlfma_ops_info": ([ctypes.c_void_p, ctypes.POINTER(LevelInfo), ctypes.c_int],
+                       ctypes.c_int),
+    "mlfma_copy_spectra": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                            ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_set_device_memory_limit": ([ctypes.c_int64], None),
+    "mlfma_profile_begin": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int64], ctypes.c_int),
+    "mlfma_profile_end": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "mlfma_last_error": ([], ctypes.c_char_p),
+}
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libmlfma.so is not built (python -m paper_2006_15367_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(status, where):
+    if status != OK:
+        raise MlfmaError(status, where)
+
+
+def set_device_memory_limit(nbytes):
+    _load().mlfma_set_device_memory_limit(int(nbytes))
+
+
+def _as_xyz(xyz):
+    if hasattr(xyz, "detach"):
+        xyz = xyz.detach().cpu().numpy()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    if xyz.ndim != 2 or xyz.shape[1] != 3:
+        raise ValueError("xyz must have shape [n, 3]")
+    return xyz
+
+
+class Tree:
+    """Octree over the points (host side; see mlfma_build_tree)."""
+
+    def __init__(self, xyz, leaf_size=0.25, max_levels=21, device=0):
+        lib = _load()
+        xyz = _as_xyz(xyz)
+        h = ctypes.c_void_p()
+        _check(lib.mlfma_build_tree(xyz.ctypes.data if xyz.size else None, xyz.shape[0],
+                                    float(leaf_size), int(max_levels), int(device),
+                                    ctypes.byref(h)), "mlfma_build_tree")
+        self._h = h
+        self.n = xyz.shape[0]
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        inf = TreeInfo()
+        _check(_load().mlfma_tree_info_get(self._h, ctypes.byref(inf)), "mlfma_tree_info_get")
+        return {"n_points": inf.n_points, "n_levels": inf.n_levels, "device": inf.device,
+                "leaf_size": inf.leaf_size, "root_size": inf.root_size,
+                "origin": tuple(inf.origin), "n_leaf_boxes": inf.n_leaf_boxes,
+                "n_near_pairs": inf.n_near_pairs, "n_p2p_pairs": inf.n_p2p_pairs}
+
+    def permutation(self):
+        p = np.empty(self.n, dtype=np.int64)
+        _check(_load().mlfma_tree_permutation(self._h, p.ctypes.data if self.n else None),
+               "mlfma_tree_permutation")
+        return p
+
+    def level(self, level):
+        """Integer box coordinates [nbox, 3] and parent indices [nbox]."""
+        lib = _load()
+        nb = ctypes.c_int64()
+        _check(lib.mlfma_tree_level(self._h, int(level), ctypes.byref(nb), None, None),
+               "mlfma_tree_level")
+        c = np.empty((nb.value, 3), dtype=np.int32)
+        p = np.empty(nb.value, dtype=np.int32)
+        _check(lib.mlfma_tree_level(self._h, int(level), ctypes.byref(nb), c.ctypes.data,
+                                    p.ctypes.data), "mlfma_tree_level")
+        return c, p
+
+    def far_list(self, level):
+        lib = _load()
+        cnt = ctypes.c_int64()
+        _check(lib.mlfma_tree_far_list(self._h, int(level), ctypes.byref(cnt), None, None, None),
+               "mlfma_tree_far_list")
+        n = cnt.value
+        obs = np.empty(n, np.int32)
+        src = np.empty(n, np.int32)
+        code = np.empty(n, np.int32)
+        _check(lib.mlfma_tree_far_list(self._h, int(level), ctypes.byref(cnt), obs.ctypes.data,
+                                       src.ctypes.data, code.ctypes.data), "mlfma_tree_far_list")
+        return obs, src, code
+
+    def near_list(self):
+        inf = self.info()
+        start = np.empty(inf["n_leaf_boxes"] + 1, np.int64)
+        idx = np.empty(inf["n_near_pairs"], np.int32)
+        _check(_load().mlfma_tree_near_list(self._h, start.ctypes.data, idx.ctypes.data),
+               "mlfma_tree_near_list")
+        return start, idx
+
+    def update_positions(self, xyz):
+        xyz = _as_xyz(xyz)
+        if xyz.shape[0] != self.n:
+            raise ValueError("point count changed")
+        _check(_load().mlfma_update_positions(self._h, xyz.ctypes.data if self.n else None),
+               "mlfma_update_positions")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().mlfma_destroy_tree(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError("charges must be complex64 or complex128, got %s" % t.dtype)
+
+
+class Operators:
+    """Precomputed operators + device workspace (see
+    mlfma_precompute_operators)."""
+
+    def __init__(self, tree, k, digits=3, max_rhs=1, bf16x3=False):
+        lib = _load()
+        h = ctypes.c_void_p()
+        flags = BF16X3_INTERP if bf16x3 else FP32
+        _check(lib.mlfma_precompute_operators(tree.handle, float(k), int(digits),
+                                              int(max_rhs), flags, ctypes.byref(h)),
+               "mlfma_precompute_operators")
+        self._h = h
+        self.tree = tree
+        self.n = tree.n
+        self.k = float(k)
+        self.max_rhs = int(max_rhs)
+        self.device = tree.device
+
+    def levels(self):
+        nl = self.tree.info()["n_levels"]
+        arr = (LevelInfo * nl)()
+        _check(_load().mlfma_ops_info(self._h, arr, nl), "mlfma_ops_info")
+        return [{f: getattr(a, f) for f, _ in LevelInfo._fields_ if f != "pad"} for a in arr]
+
+    def _prep(self, q, comps=1):
+        import torch
+        if not (isinstance(q, torch.Tensor) and q.is_cuda):
+            raise TypeError("expected a CUDA (HIP) tensor")
+        if q.shape[0] != self.n or q.dim() not in (1, 2):
+            raise ValueError("expected shape [n] or [n, nrhs] with n = %d" % self.n)
+        q = q.contiguous()
+        nrhs = 1 if q.dim() == 1 else q.shape[1]
+        shape = tuple(q.shape) + ((comps,) if comps > 1 else ())
+        out = torch.empty(shape, dtype=q.dtype, device=q.device)
+        return q, out, nrhs
+
+    def matvec_ex(self, q, parts=NEAR | FAR, stream=None):
+        q, out, nrhs = self._prep(q)
+        _check(_load().mlfma_matvec_ex(self._h, q.data_ptr(), out.data_ptr(), nrhs,
+                                       _dtype_code(q), parts, _stream_ptr(stream)),
+               "mlfma_matvec_ex")
+        return out
+
+    def matvec(self, q, stream=None):
+        q, out, nrhs = self._prep(q)
+        _check(_load().mlfma_matvec(self._h, q.data_ptr(), out.data_ptr(), nrhs,
+                                    _dtype_code(q), _stream_ptr(stream)), "mlfma_matvec")
+        return out
+
+    def adjoint(self, v, stream=None):
+        v, out, nrhs = self._prep(v)
+        _check(_load().mlfma_matvec_adjoint(self._h, v.data_ptr(), out.data_ptr(), nrhs,
+                                            _dtype_code(v), _stream_ptr(stream)),
+               "mlfma_matvec_adjoint")
+        return out
+
+    def field(self, q, parts=0, stream=None):
+        q, out, nrhs = self._prep(q, comps=3)
+        _check(_load().mlfma_field(self._h, q.data_ptr(), out.data_ptr(), nrhs,
+                                   _dtype_code(q), parts, _stream_ptr(stream)), "mlfma_field")
+        return out
+
+    def copy_spectra(self, level, which, nrhs=1, stream=None):
+        import torch
+        lv = self.levels()[level - 1]
+        out = torch.empty((lv["nbox"], nrhs, lv["K"]), dtype=torch.complex64,
+                          device="cuda:%d" % self.device)
+        _check(_load().mlfma_copy_spectra(self._h, int(level), int(which), int(nrhs),
+                                          out.data_ptr(), _stream_ptr(stream)),
+               "mlfma_copy_spectra")
+        return out
+
+    def profile_begin(self, kernels=None, max_launches=4096):
+        """Start HIP-event timing of the named kernels (default: all)."""
+        names = KERNELS if kernels is None else kernels
+        mask = 0
+        for nme in names:
+            mask |= 1 << KERNELS.index(nme)
+        _check(_load().mlfma_profile_begin(self._h, mask, int(max_launches)),
+               "mlfma_profile_begin")
+
+    def profile_end(self):
+        """{kernel: (total ms, launches)} for the timed launches."""
+        ms = np.zeros(len(KERNELS), np.float64)
+        cnt = np.zeros(len(KERNELS), np.int64)
+        _check(_load().mlfma_profile_end(self._h, ms.ctypes.data, cnt.ctypes.data),
+               "mlfma_profile_end")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS) if cnt[i]}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().mlfma_destroy_ops(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

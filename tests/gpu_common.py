@@ -1,0 +1,24 @@
+"""Helpers shared by the GPU tests (no method arithmetic here)."""
+import sys
+
+import numpy as np
+import pytest
+
+
+def say(*a):
+    """Name the case on stdout before a GPU step (flushed)."""
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cuda_or_skip():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))

@@ -1,0 +1,142 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Stage by stage on the 4,096-point sphere (leaf spectra, multipoles per
+level, local expansions per level, near and far parts), then end to end
+against the dense definition; adjoint, multi-RHS and dtype checks."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import cuda_or_skip, rel_l2, say
+
+from paper_2006_15367_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+K = W.K_WAVENUMBER
+
+
+@pytest.fixture(scope="module")
+def c1():
+    torch = cuda_or_skip()
+    from oracle import dense
+    from oracle import mlfma as M
+    from paper_2006_15367_amd import mlfma as G
+    xyz, q = W.make("sphere4k")
+    ot = M.Tree(xyz, W.LEAF_SIZE)
+    oops = M.Operators(ot, K, W.DIGITS)
+    ophi, inter = M.matvec(ot, oops, q, keep=True)
+    dense_phi = dense.potential(xyz, q, K)
+    say("c1: building GPU tree/operators (sphere4k, N=4096)")
+    gt = G.Tree(xyz, W.LEAF_SIZE)
+    gops = G.Operators(gt, K, W.DIGITS, max_rhs=4)
+    return dict(torch=torch, xyz=xyz, q=q, ot=ot, oops=oops, ophi=ophi, inter=inter,
+                dense=dense_phi, gt=gt, gops=gops, G=G)
+
+
+def _run(c, fn, *args, **kw):
+    torch = c["torch"]
+    out = fn(*args, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_levels_match_oracle(c1):
+    lv = c1["gops"].levels()
+    ot, oops = c1["ot"], c1["oops"]
+    for l in range(3, ot.n_lev + 1):
+        assert lv[l - 1]["L"] == oops.L[l]
+        assert lv[l - 1]["nbox"] == ot.levels[l].nbox
+        assert lv[l - 1]["K"] == oops.grid[l].K
+
+
+def test_stage_spectra(c1):
+    torch = c1["torch"]
+    say("c1: matvec for stage spectra")
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    _run(c1, c1["gops"].matvec, qd)
+    ot, inter = c1["ot"], c1["inter"]
+    for l in range(3, ot.n_lev + 1):
+        S = c1["gops"].copy_spectra(l, 0).cpu().numpy()
+        Lg = c1["gops"].copy_spectra(l, 1).cpu().numpy()
+        torch.cuda.synchronize()
+        e_s = rel_l2(S, inter["S"][l])
+        e_l = rel_l2(Lg, inter["L"][l])
+        say("level", l, "multipole rel err", e_s, "local rel err", e_l)
+        assert e_s < 1e-5
+        assert e_l < 1e-4
+
+
+def test_near_and_far_parts(c1):
+    torch = c1["torch"]
+    G = c1["G"]
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    perm = c1["ot"].perm
+    say("c1: near part")
+    near = _run(c1, c1["gops"].matvec_ex, qd, parts=G.NEAR)
+    near_o = np.empty_like(c1["inter"]["near"][:, 0])
+    near_o[perm] = c1["inter"]["near"][:, 0]
+    assert rel_l2(near, near_o) < 1e-5
+    say("c1: far part")
+    far = _run(c1, c1["gops"].matvec_ex, qd, parts=G.FAR)
+    far_o = np.empty_like(near_o)
+    far_o[perm] = c1["inter"]["far"][:, 0]
+    assert rel_l2(far, far_o) < 1e-4
+
+
+def test_end_to_end_vs_dense_and_oracle(c1):
+    torch = c1["torch"]
+    say("c1: end to end, complex128 input")
+    qd = torch.from_numpy(c1["q"]).cuda()          # complex128 at the boundary
+    phi = _run(c1, c1["gops"].matvec, qd)
+    assert phi.dtype == np.complex128
+    e_dense = rel_l2(phi, c1["dense"])
+    e_orc = rel_l2(phi, c1["ophi"])
+    say("rel L2 vs dense", e_dense, "vs FP64 MLFMA", e_orc)
+    assert e_dense < 1e-3
+    assert e_orc < 1e-4
+
+
+def test_adjoint(c1):
+    torch = c1["torch"]
+    rng = np.random.default_rng(31)
+    n = c1["xyz"].shape[0]
+    x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    y = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    say("c1: adjoint")
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    Ax = _run(c1, c1["gops"].matvec, xd).astype(np.complex128)
+    Ahy = _run(c1, c1["gops"].adjoint, yd).astype(np.complex128)
+    lhs = np.vdot(y, Ax)
+    rhs = np.vdot(Ahy, x)
+    # random vectors: |<y, Ax>| ~ |y||Ax|/sqrt(n), so scale by the norms
+    assert abs(lhs - rhs) < 1e-5 * np.linalg.norm(y) * np.linalg.norm(Ax)
+    # the adjoint is the conjugate pass: compare with the oracle's adjoint
+    from oracle import mlfma as M
+    ref = M.adjoint(c1["ot"], c1["oops"], y.astype(np.complex128))
+    assert rel_l2(Ahy, ref) < 1e-4
+
+
+def test_multi_rhs_equals_single(c1):
+    torch = c1["torch"]
+    rng = np.random.default_rng(32)
+    n = c1["xyz"].shape[0]
+    Q = (rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))).astype(np.complex64)
+    say("c1: 3 right-hand sides")
+    P = _run(c1, c1["gops"].matvec, torch.from_numpy(Q).cuda())
+    for r in range(3):
+        p = _run(c1, c1["gops"].matvec, torch.from_numpy(np.ascontiguousarray(Q[:, r])).cuda())
+        assert rel_l2(P[:, r], p) < 1e-6
+
+
+def test_field_vs_dense(c1):
+    torch = c1["torch"]
+    from oracle import dense
+    say("c1: field")
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    F = _run(c1, c1["gops"].field, qd)
+    ref = dense.field(c1["xyz"], c1["q"], K)
+    e = rel_l2(F, ref)
+    say("field rel L2 vs dense", e)
+    assert e < 1e-3
