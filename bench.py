@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--bf16x3", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU path is not part of this "
@@ -161,6 +164,12 @@ def main():
     qd = torch.from_numpy(np.ascontiguousarray(q.astype(np.complex64))).cuda()
     vd = torch.from_numpy(np.ascontiguousarray(np.conj(q).astype(np.complex64))).cuda()
 
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         phi = ops.matvec(qd)
     torch.cuda.synchronize()
@@ -210,6 +219,7 @@ def main():
                     "ms_per_step": round(adj_ms, 4)},
         "setup_s": {"tree": round(t1 - t0, 3), "operators": round(t2 - t1, 3)},
         "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
+        "m2l_variant_per_level": ops.variants("m2l"),
         "roofline": rl,
     }
     if not args.no_cpu_baseline:

@@ -68,8 +68,10 @@ enum mlfma_parts {
 /* mlfma_precompute_operators flags */
 enum mlfma_flags {
     MLFMA_FP32 = 0,          /* FP32 interpolation / anterpolation GEMMs     */
-    MLFMA_BF16X3_INTERP = 1  /* interpolation GEMMs in BF16 split precision
+    MLFMA_BF16X3_INTERP = 1, /* interpolation GEMMs in BF16 split precision
                                 (hi*hi + hi*lo + lo*hi, FP32 accumulation)  */
+    MLFMA_NO_AUTOTUNE = 2    /* skip the kernel-variant timing at precompute
+                                (variants differ only in summation order)   */
 };
 
 typedef struct mlfma_tree_info {
@@ -258,6 +260,17 @@ enum mlfma_kernel_id {
 int mlfma_profile_begin(mlfma_ops_t ops, uint32_t kernel_mask,
                         int64_t max_launches);
 int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
+
+/*
+ * Diagnostics: the kernel variant the autotuner chose for each level
+ * (out[l-1] for levels 1..n_levels; -1 where a level has no such kernel).
+ * kernel = MLFMA_K_M2L: 0 per-observer lists from L2, 1 operators staged in
+ * LDS, 2 sibling groups, 3 sibling groups with per-source records.
+ */
+int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
+/* Diagnostics: force a variant of `kernel` on `level` (3..n_levels); used by
+ * the tests to check every variant.  EINVAL for an unknown variant. */
+int mlfma_ops_set_variant(mlfma_ops_t ops, int kernel, int level, int variant);
 
 /*
  * Cap on the device bytes mlfma_precompute_operators may allocate (0 = no

@@ -3,6 +3,7 @@
 // L2O, plus the leaf-level near field).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -35,6 +36,13 @@ struct DevLevel {
     int32_t *parent = nullptr;       // into level-1
     uint8_t *oct = nullptr;          // octant of the box inside its parent
     int32_t *child_start = nullptr;  // into level+1
+    int32_t *nbr_start = nullptr, *nbr_idx = nullptr;  // neighbours at this level
+    int32_t *base = nullptr;         // 49 cx + 7 cy + cz
+    int16_t *typemap = nullptr;      // [343] offset code -> operator or -1
+    int m2l_variant = 0;             // 0 per-observer (L2), 1 operators in LDS, 2 sibling groups,
+                                     // 3 sibling groups with per-source records
+    int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
+    int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     float2 *S = nullptr, *Lloc = nullptr;  // [nbox][R][K]
     int Lc = 0, Mc = 0;
     float2 *shift = nullptr;
@@ -57,6 +65,8 @@ struct mlfma_ops_s {
     float4 *pts = nullptr;
     int32_t *perm = nullptr, *pt_leaf = nullptr, *pt_start = nullptr;
     int32_t *near_start = nullptr, *near_idx = nullptr, *leaf_coord = nullptr;
+    int2 *p2p_items = nullptr;       // (leaf, first target) per 64-target chunk
+    int64_t n_p2p_items = 0;
     float2 *qs = nullptr, *near = nullptr;
     float2 *X1 = nullptr, *X2 = nullptr;
     int64_t scratch_elems = 0;
@@ -196,6 +206,69 @@ int refresh_positions(mlfma_ops_s *o)
 }
 
 // ---------------------------------------------------------------- matvec --
+hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s)
+{
+    DevLevel &D = o->lev[l];
+    DevLevel &Pl = o->lev[l - 1];
+    switch (variant) {
+    case 1:
+        return dev::m2l_lds(D.nbox, D.K, D.ntypes, D.far_start, D.far_src, D.far_type, D.T, D.S,
+                            R, D.Lloc, s);
+    case 2:
+        return dev::m2l_sg(Pl.nbox, D.K, D.ntypes, Pl.child_start, Pl.nbr_start, Pl.nbr_idx,
+                           D.base, D.typemap, D.T, D.S, R, D.Lloc, s);
+    case 3:
+        return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
+                            D.rec_off, D.T, D.S, R, D.Lloc, s);
+    default:
+        return dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s);
+    }
+}
+
+// Autotuner: per level, time every M2L variant (HIP events, 3 runs each,
+// best of 3) at the handle's max_rhs and keep the fastest.  The results of
+// the variants are identical up to summation order.
+int autotune_m2l(mlfma_ops_s *o)
+{
+    if (o->n_lev < 3) return MLFMA_OK;
+    hipStream_t s;
+    if (hipStreamCreate(&s) != hipSuccess) return fail(MLFMA_EDEVICE, "autotune: stream");
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int rc = MLFMA_OK;
+    for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
+        float best = 1e30f;
+        int bestv = 0;
+        for (int v = 0; v < 4; ++v) {
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                (void)hipEventRecord(e0, s);
+                hipError_t e = launch_m2l(o, l, v, o->max_rhs, s);
+                (void)hipEventRecord(e1, s);
+                if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed: %s", v,
+                              hipGetErrorString(e));
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tmin = std::min(tmin, ms);
+            }
+            if (rc) break;
+            if (tmin < best) {
+                best = tmin;
+                bestv = v;
+            }
+        }
+        o->lev[l].m2l_variant = bestv;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
 // The far field: C2M, M2M up the tree, M2L per level, L2L down the tree.
 // Leaves the leaf-level local expansions in lev[n_lev].Lloc.
 int run_far(mlfma_ops_s *o, int R, hipStream_t s)
@@ -207,14 +280,14 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s)
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
-        LAUNCH(MLFMA_K_INTERP_S1, dev::dft_rows(C.S, C.nbox * R * C.nth, C.nph, P.iF, M, o->X1, s));
+        LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s));
         LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s));
         LAUNCH(MLFMA_K_INTERP_S3, dev::interp_s3(P.nbox, R, P.nth, P.nph, M, P.child_start, C.oct, o->X2, P.iG,
                           P.shift, P.S, s));
     }
     for (int l = 3; l <= nl; ++l) {
         DevLevel &D = o->lev[l];
-        LAUNCH(MLFMA_K_M2L, dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s));
+        LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s));
     }
     for (int l = 3; l < nl; ++l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
@@ -254,9 +327,10 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
             LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, conj, o->qs, s));
             const int64_t nnear = o->n * R * (field ? 3 : 1);
             if (parts & MLFMA_NEAR)
-                LAUNCH(MLFMA_K_P2P, dev::p2p(o->pts, o->pt_leaf, o->pt_start, o->near_start, o->near_idx,
-                            o->leaf_coord, (float)o->tree->leaf, (float)o->k, o->qs, o->n, R,
-                            field, o->near, s));
+                LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->pts, o->pt_start,
+                                             o->near_start, o->near_idx, o->leaf_coord,
+                                             (float)o->tree->leaf, (float)o->k, o->qs, R, field,
+                                             o->near, s));
             else
                 LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
             if (far) {
@@ -310,7 +384,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     if (digits < 1 || digits > 10) return fail(MLFMA_EINVAL, "precompute: digits outside 1..10");
     if (max_rhs < 1 || max_rhs > 1024)
         return fail(MLFMA_EINVAL, "precompute: max_rhs outside 1..1024");
-    if (flags & ~(uint32_t)MLFMA_BF16X3_INTERP)
+    if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE))
         return fail(MLFMA_EINVAL, "precompute: unknown flags");
     if (t->n_lev >= 3 && k * std::sqrt(3.0) * t->leaf < 1.0)
         return fail(MLFMA_EINVAL,
@@ -343,6 +417,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     pl.add((nleaf + 1) * 4 * 2);       // pt_start, near_start
     pl.add((int64_t)t->near_idx.size() * 4);
     pl.add(nleaf * 12);
+    pl.add((t->n / 64 + nleaf + 1) * 8);  // P2P work items
     pl.add(t->n * R * 8);              // qs
     pl.add(t->n * R * 8 * 3);          // near (3 components for the field)
     int64_t scratch = 0;
@@ -356,6 +431,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             pl.add((int64_t)H.far_src.size() * 6);
             pl.add(H.nbox * 5);
             pl.add((H.nbox + 1) * 4);
+            pl.add(H.nbox * 4 + 343 * 2 + (H.nbox + 1) * 4 + 26 * H.nbox * 4);
+            pl.add((int64_t)H.far_src.size() * 36 + (H.nbox + 1) * 4);  // M2L records (bound)
             pl.add(H.nbox * R * T.K * 8 * 2);
             if (l < nl) {
                 const LevelTables &C = o->tab[l + 1];
@@ -396,11 +473,27 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         if ((r = upload(o, &o->near_start, v32.data(), (int64_t)v32.size()))) return r;
         if ((r = upload(o, &o->near_idx, t->near_idx.data(), (int64_t)t->near_idx.size()))) return r;
         if ((r = upload(o, &o->leaf_coord, t->lev[nl].coord.data(), 3 * nleaf))) return r;
+        std::vector<int2> items;
+        for (int64_t b = 0; b < nleaf; ++b)
+            for (int64_t t0 = 0; t0 < t->pt_start[b + 1] - t->pt_start[b]; t0 += 64)
+                items.push_back(make_int2((int)b, (int)t0));
+        o->n_p2p_items = (int64_t)items.size();
+        if ((r = upload(o, &o->p2p_items, items.data(), o->n_p2p_items))) return r;
         if ((r = dalloc(o, &o->qs, t->n * R))) return r;
         if ((r = dalloc(o, &o->near, t->n * R * 3))) return r;
         o->lev.resize(nl + 1);
         for (int l = 1; l <= nl; ++l) o->lev[l].nbox = t->lev[l].nbox;
         if (nl < 3) return MLFMA_OK;
+        // parents of the far-field levels: child ranges and neighbour lists
+        for (int l = 2; l < nl; ++l) {
+            DevLevel &D = o->lev[l];
+            const HostLevel &H = t->lev[l];
+            if ((r = upload(o, &D.child_start, H.child_start.data(), H.nbox + 1))) return r;
+            std::vector<int32_t> ns, ni;
+            neighbour_lists(*t, l, ns, ni);
+            if ((r = upload(o, &D.nbr_start, ns.data(), (int64_t)ns.size()))) return r;
+            if ((r = upload(o, &D.nbr_idx, ni.data(), (int64_t)ni.size()))) return r;
+        }
         for (int l = 3; l <= nl; ++l) {
             DevLevel &D = o->lev[l];
             const LevelTables &T = o->tab[l];
@@ -424,8 +517,55 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             if ((r = upload(o, &D.oct, oc.data(), H.nbox))) return r;
             if ((r = dalloc(o, &D.S, H.nbox * R * T.K))) return r;
             if ((r = dalloc(o, &D.Lloc, H.nbox * R * T.K))) return r;
+            {
+                // per-source records of the parents (level l-1) of this level
+                const HostLevel &HP = t->lev[l - 1];
+                std::vector<int32_t> ns, ni;
+                neighbour_lists(*t, l - 1, ns, ni);
+                std::vector<int32_t> rs(HP.nbox + 1, 0), rsrc, roff;
+                const int32_t zero_row = T.ntypes * 64 * (int32_t)sizeof(float2);
+                for (int64_t p = 0; p < HP.nbox; ++p) {
+                    const int32_t o0 = HP.child_start[p], o1 = HP.child_start[p + 1];
+                    for (int32_t e = ns[p]; e < ns[p + 1]; ++e) {
+                        const int32_t q = ni[e];
+                        for (int32_t sb = HP.child_start[q]; sb < HP.child_start[q + 1]; ++sb) {
+                            uint16_t ty[8];
+                            bool any = false;
+                            for (int i = 0; i < 8; ++i) {
+                                ty[i] = 0xffff;
+                                if (o0 + i >= o1) continue;
+                                const int32_t *co = &H.coord[3 * (o0 + i)], *cs = &H.coord[3 * sb];
+                                const int dx = co[0] - cs[0], dy = co[1] - cs[1], dz = co[2] - cs[2];
+                                if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) < 2)
+                                    continue;
+                                const int code = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
+                                const int16_t tt = T.code_to_type[code];
+                                if (tt >= 0) {
+                                    ty[i] = (uint16_t)tt;
+                                    any = true;
+                                }
+                            }
+                            if (!any) continue;
+                            rsrc.push_back(sb);
+                            for (int i = 0; i < 8; ++i)
+                                roff.push_back(ty[i] == 0xffff ? zero_row
+                                                               : (int32_t)ty[i] * 64 * (int32_t)sizeof(float2));
+                        }
+                    }
+                    rs[p + 1] = (int32_t)rsrc.size();
+                }
+                if ((r = upload(o, &D.rec_start, rs.data(), (int64_t)rs.size()))) return r;
+                if ((r = upload(o, &D.rec_src, rsrc.data(), (int64_t)rsrc.size()))) return r;
+                if ((r = upload(o, &D.rec_off, roff.data(), (int64_t)roff.size()))) return r;
+            }
+            {
+                std::vector<int32_t> bs(H.nbox);
+                for (int64_t b = 0; b < H.nbox; ++b)
+                    bs[b] = 49 * H.coord[3 * b] + 7 * H.coord[3 * b + 1] + H.coord[3 * b + 2];
+                if ((r = upload(o, &D.base, bs.data(), H.nbox))) return r;
+                if ((r = upload(o, &D.typemap, T.code_to_type.data(), 343))) return r;
+            }
             if (l < nl) {
-                if ((r = upload(o, &D.child_start, H.child_start.data(), H.nbox + 1))) return r;
                 D.Lc = T.Lc;
                 D.Mc = T.Mc;
                 if ((r = upload(o, &D.shift, (const float2 *)T.shift.data(), 8 * T.K))) return r;
@@ -440,6 +580,15 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         o->scratch_elems = scratch;
         if ((r = dalloc(o, &o->X1, scratch))) return r;
         if ((r = dalloc(o, &o->X2, scratch))) return r;
+        // spectra start zeroed (the autotuner runs M2L on them)
+        for (int l = 3; l <= nl; ++l) {
+            DevLevel &D = o->lev[l];
+            if (hipMemset(D.S, 0, (size_t)(D.nbox * R * D.K) * sizeof(float2)) != hipSuccess)
+                return fail(MLFMA_EDEVICE, "hipMemset failed");
+        }
+        if (!(flags & MLFMA_NO_AUTOTUNE)) {
+            if ((r = autotune_m2l(o))) return r;
+        }
         return MLFMA_OK;
     }();
     (void)hipSetDevice(cur);
@@ -577,6 +726,25 @@ int mlfma_copy_spectra(mlfma_ops_t o, int level, int which, int64_t nrhs, void *
     hipError_t e = hipMemcpyAsync(dst, src, (size_t)(D.nbox * nrhs * D.K) * sizeof(float2),
                                   hipMemcpyDeviceToDevice, (hipStream_t)stream);
     return check_hip(e, "copy_spectra");
+}
+
+int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
+{
+    if (!o || !out) return fail(MLFMA_EINVAL, "ops_variants: null argument");
+    if (kernel != MLFMA_K_M2L) return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
+    for (int l = 1; l <= o->n_lev && l <= max_entries; ++l)
+        out[l - 1] = l >= 3 ? o->lev[l].m2l_variant : -1;
+    return MLFMA_OK;
+}
+
+int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
+{
+    if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
+    if (kernel != MLFMA_K_M2L) return fail(MLFMA_EINVAL, "ops_set_variant: kernel %d has no variants", kernel);
+    if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
+    if (variant < 0 || variant > 3) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+    o->lev[level].m2l_variant = variant;
+    return MLFMA_OK;
 }
 
 int mlfma_profile_begin(mlfma_ops_t o, uint32_t kernel_mask, int64_t max_launches)

@@ -52,6 +52,9 @@ int build_tree(const double *xyz, int64_t n, double leaf, int max_levels,
                int device, Tree **out);
 int update_positions(Tree *t, const double *xyz);
 void release_tree(Tree *t);
+// boxes of level l at Chebyshev distance 1 (the box itself excluded), CSR
+void neighbour_lists(const Tree &t, int l, std::vector<int32_t> &start,
+                     std::vector<int32_t> &idx);
 
 // Host (FP64) tables of one level l >= 3, stored in FP32 for the device.
 struct LevelTables {
@@ -67,10 +70,10 @@ struct LevelTables {
     int Lc = 0, Mc = 0;              // child order, 2 Lc + 1 real-DFT columns
     std::vector<float> shift;        // [8][K][2] exp(-i k khat.(c_c - c_p))
     std::vector<float> iF;           // [nph_c][Mc]   child-grid real DFT
-    std::vector<float> iA;           // [Lc+1][nth][nth_c] theta maps
+    std::vector<float> iA;           // [Lc+1][nth_c][nth] theta maps (input index first)
     std::vector<float> iG;           // [Mc][nph]     parent-grid synthesis
     std::vector<float> aF;           // [nph][Mc]     parent-grid real DFT
-    std::vector<float> aB;           // [Lc+1][nth_c][nth] theta maps
+    std::vector<float> aB;           // [Lc+1][nth][nth_c] theta maps (input index first)
     std::vector<float> aG;           // [Mc][nph_c]   child-grid synthesis
 };
 

@@ -1,0 +1,575 @@
+// Interpolation (M2M, Sec. 3.2.2) and anterpolation (L2L, Sec. 3.2.4) as
+// dense contractions on the matrix cores (gfx950 MFMA).
+//
+// The exact band-limited map between two sample grids is three real
+// matrices applied to complex spectra:
+//   s1  phi-DFT       [rows = (box, rhs, theta_in)] x F [nphi_in x M]
+//   s2  theta map     per Fourier column m: [rows = (box, rhs)] x A_m^T
+//   s3  phi-synthesis [rows = (box, rhs, theta_out)] x G [M x nphi_out]
+// Each stage is a "row GEMM": C[rows x N] = A[rows x K] * B[K x N] with A
+// complex (data) and B real (operator).  The intermediates are written
+// transposed so that every stage reads K-contiguous rows:
+//   s1 writes T1[col][(box, rhs)][theta_in]
+//   s2 writes T2[(box, rhs)][col][theta_out]
+// M2M s3 fuses the shift exp(-ik khat.(c_c - c_p)) and the sum over the
+// siblings (parent-centric, no atomics); L2L s1 fuses the conjugate shift of
+// the parent's local expansion and L2L s3 adds into the child's local.
+//
+// MFMA mapping (v_mfma_f32_16x16x4_f32, D = A(16x4) B(4x16) + C): one wave
+// computes 8 complex rows x 16 columns per instruction.  MFMA row 2t+h is
+// the real (h=0) or imaginary (h=1) part of complex row t; lane l feeds
+// A[l%16][l/16] and B[l/16][l%16] and receives D[4(l/16)+v][l%16], i.e. the
+// complex values of rows 2(l/16) (v=0,1) and 2(l/16)+1 (v=2,3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace mlfma {
+namespace dev {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+static inline unsigned waves_to_blocks(int64_t waves) { return (unsigned)((waves + 3) / 4); }
+
+// ------------------------------------------------------- problem types --
+// M2M s1: rows (c, r, theta) of the child spectra, K = nphi_c, N = M.
+struct ProbS1 {
+    static constexpr bool rows_fast = false;
+    const float2 *X;
+    const float *F;
+    float2 *out;
+    int64_t nrows, BR;
+    int K, N, nth;
+    __device__ float2 a(int64_t row, int k) const { return X[row * K + k]; }
+    __device__ float b(int k, int n) const { return F[k * N + n]; }
+    __device__ void store(int64_t row, int n, float2 v) const
+    {
+        const int64_t cr = row / nth;
+        const int th = (int)(row - cr * nth);
+        out[((int64_t)n * BR + cr) * nth + th] = v;
+    }
+    __device__ void set_col(int) {}
+};
+
+// L2L s1: rows (c, r, theta_p); A = conj(shift[oct c]) * L_parent(c).
+struct ProbS1L {
+    static constexpr bool rows_fast = false;
+    const float2 *Lp, *shift;
+    const int32_t *parent;
+    const uint8_t *oct;
+    const float *F;
+    float2 *out;
+    int64_t nrows, BR, Kp;
+    int K, N, nth, R;
+    __device__ float2 a(int64_t row, int k) const
+    {
+        const int cr = (int)row / nth;
+        const int th = (int)row - cr * nth;
+        const int c = cr / R;
+        const int r = cr - c * R;
+        const float2 x = Lp[((int64_t)parent[c] * R + r) * Kp + th * K + k];
+        const float2 s = shift[(int64_t)oct[c] * Kp + th * K + k];
+        return make_float2(s.x * x.x + s.y * x.y, s.x * x.y - s.y * x.x);
+    }
+    __device__ float b(int k, int n) const { return F[k * N + n]; }
+    __device__ void store(int64_t row, int n, float2 v) const
+    {
+        const int64_t cr = row / nth;
+        const int th = (int)(row - cr * nth);
+        out[((int64_t)n * BR + cr) * nth + th] = v;
+    }
+    __device__ void set_col(int) {}
+};
+
+// s2 for one Fourier column `col`: rows (c, r), K = nth_in, N = nth_out,
+// B(k, n) = mapsT[m][k][n].
+struct ProbS2 {
+    const float2 *T1;
+    const float *maps;
+    float2 *out;
+    int64_t nrows;  // BR
+    int K, N, M, col;
+    __device__ float2 a(int64_t row, int k) const
+    {
+        return T1[((int64_t)col * nrows + row) * K + k];
+    }
+    __device__ float b(int k, int n) const
+    {
+        const int m = (col + 1) >> 1;
+        return maps[((int64_t)m * K + k) * N + n];
+    }
+    __device__ void store(int64_t row, int n, float2 v) const
+    {
+        out[(row * M + col) * N + n] = v;
+    }
+    __device__ void set_col(int c) { col = c; }
+    static constexpr bool rows_fast = false;
+};
+
+// L2L s3: rows (c, r, theta_c), K = M, N = nphi_c; adds into the local.
+// T2 is [(c, r)][col][theta_c], so consecutive rows are contiguous for a
+// fixed k (rows_fast: the LDS staging walks rows fastest).
+struct ProbS3L {
+    const float2 *T2;
+    const float *G;
+    float2 *Lc;
+    int64_t nrows;
+    int K, N, nth;
+    static constexpr bool rows_fast = true;
+    __device__ float2 a(int64_t row, int k) const
+    {
+        const int cr = (int)row / nth;
+        const int th = (int)row - cr * nth;
+        return T2[((int64_t)cr * K + k) * nth + th];
+    }
+    __device__ float b(int k, int n) const { return G[k * N + n]; }
+    __device__ void store(int64_t row, int n, float2 v) const
+    {
+        float2 *p = Lc + row * N + n;
+        float2 o = *p;
+        o.x += v.x;
+        o.y += v.y;
+        *p = o;
+    }
+    __device__ void set_col(int) {}
+};
+
+// ------------------------------------------------ generic wave row GEMM --
+// A workgroup of 4 waves takes 32 complex rows (8 per wave).  The real
+// operator is staged in LDS once per workgroup, 16*NT columns at a time
+// (NT chosen so that the staged block is <= 64 KB); the data rows stream
+// from global memory, one float per lane per k-step.
+__device__ __forceinline__ int64_t xcd_contiguous_i(int64_t bid, int64_t nb)
+{
+    const int64_t q = nb / 8, rem = nb % 8;
+    const int64_t x = bid % 8, i = bid / 8;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+template <class P, int NT>
+__device__ __forceinline__ void wave_tile(const P &p, const float *Bs, int64_t row0, int n0,
+                                          int lane)
+{
+    constexpr int NC = 16 * NT;
+    const int t = (lane & 15) >> 1, part = lane & 1, kq = lane >> 4;
+    const int64_t myrow = row0 + t;
+    const bool rv = myrow < p.nrows;
+    floatx4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int kb = 0;
+    for (; kb + 8 <= p.K; kb += 8) {
+        float av[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float2 x = rv ? p.a(myrow, kb + 4 * u + kq) : make_float2(0.f, 0.f);
+            av[u] = part ? x.y : x.x;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[j] = mfma4(av[u], Bs[(kb + 4 * u + kq) * NC + 16 * j + (lane & 15)], acc[j]);
+    }
+    for (; kb < p.K; kb += 4) {
+        const int k = kb + kq;
+        float av = 0.f;
+        if (rv && k < p.K) {
+            const float2 x = p.a(myrow, k);
+            av = part ? x.y : x.x;
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const float bv = k < p.K ? Bs[k * NC + 16 * j + (lane & 15)] : 0.f;
+            acc[j] = mfma4(av, bv, acc[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int n = n0 + 16 * j + (lane & 15);
+        if (n < p.N) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t row = row0 + 2 * kq + h;
+                if (row < p.nrows) p.store(row, n, make_float2(acc[j][2 * h], acc[j][2 * h + 1]));
+            }
+        }
+    }
+}
+
+template <class P, int NT>
+__device__ __forceinline__ void stage_b(const P &p, float *Bs, int n0)
+{
+    constexpr int NC = 16 * NT;
+    for (int base = threadIdx.x; base < p.K * NC; base += 8 * blockDim.x) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int k = idx / NC, n = idx - (idx / NC) * NC;
+            v[u] = (idx < p.K * NC && n0 + n < p.N) ? p.b(k, n0 + n) : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < p.K * NC) Bs[idx] = v[u];
+        }
+    }
+}
+
+template <class P, int NT>
+__global__ void __launch_bounds__(256) k_rowgemm(P p)
+{
+    extern __shared__ float Bs[];
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = xcd_contiguous_i(blockIdx.x, gridDim.x);
+    const int64_t row0 = (blk * 4 + (threadIdx.x >> 6)) * 8;
+    for (int n0 = 0; n0 < p.N; n0 += 16 * NT) {
+        __syncthreads();
+        stage_b<P, NT>(p, Bs, n0);
+        __syncthreads();
+        if (row0 < p.nrows) wave_tile<P, NT>(p, Bs, row0, n0, lane);
+    }
+}
+
+// s2: one Fourier column per blockIdx.y
+template <int NT>
+__global__ void __launch_bounds__(256) k_s2(ProbS2 p)
+{
+    extern __shared__ float Bs[];
+    p.col = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8;
+    for (int n0 = 0; n0 < p.N; n0 += 16 * NT) {
+        __syncthreads();
+        stage_b<ProbS2, NT>(p, Bs, n0);
+        __syncthreads();
+        if (row0 < p.nrows) wave_tile<ProbS2, NT>(p, Bs, row0, n0, lane);
+    }
+}
+
+// Same contraction with the data tile staged in LDS as well: a workgroup
+// loops over tiles of 32 complex rows (grid-stride), copies each tile with
+// coalesced loads into LDS, and its 4 waves read their MFMA fragments from
+// LDS.  The operator block is staged once per workgroup and column chunk.
+// Used when K <= 128.
+template <class P, int NT>
+__global__ void __launch_bounds__(256) k_rowgemm_lds(P p, int col_override)
+{
+    extern __shared__ float smem[];
+    constexpr int NC = 16 * NT;
+    const int K = p.K;
+    const int KP = ((K + 3) & ~3) + 1;        // row pitch in float2 (odd: spreads banks)
+    float *Bs = smem;                         // [K4][NC]
+    float2 *As = (float2 *)(smem + ((K + 3) & ~3) * NC);  // [32][KP]
+    if (col_override >= 0) p.set_col(col_override + blockIdx.y);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = (lane & 15) >> 1, part = lane & 1, kq = lane >> 4;
+    const int64_t ntiles = (p.nrows + 31) / 32;
+    const int K4 = (K + 3) & ~3;
+    for (int n0 = 0; n0 < p.N; n0 += NC) {
+        __syncthreads();
+        for (int base = threadIdx.x; base < K4 * NC; base += 8 * blockDim.x) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * blockDim.x;
+                const int k = idx / NC, n = idx - (idx / NC) * NC;
+                v[u] = (idx < K4 * NC && k < K && n0 + n < p.N) ? p.b(k, n0 + n) : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * blockDim.x;
+                if (idx < K4 * NC) Bs[idx] = v[u];
+            }
+        }
+        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int64_t rbase = tile * 32;
+            __syncthreads();
+            for (int base = threadIdx.x; base < 32 * K4; base += 4 * blockDim.x) {
+                float2 v[4];
+                int dst[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = base + u * blockDim.x;
+                    int rl, k;
+                    if (P::rows_fast) {
+                        k = idx >> 5;
+                        rl = idx & 31;
+                    } else {
+                        rl = idx / K4;
+                        k = idx - rl * K4;
+                    }
+                    const int64_t row = rbase + rl;
+                    dst[u] = idx < 32 * K4 ? rl * KP + k : -1;
+                    v[u] = (dst[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
+                                                                    : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (dst[u] >= 0) As[dst[u]] = v[u];
+            }
+            __syncthreads();
+            const int64_t row0 = rbase + wave * 8;
+            if (row0 >= p.nrows) continue;
+            const float2 *arow = As + (wave * 8 + t) * KP;
+            floatx4 acc[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int kb = 0; kb < K4; kb += 4) {
+                const float2 x = arow[kb + kq];
+                const float av = part ? x.y : x.x;
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[j] = mfma4(av, Bs[(kb + kq) * NC + 16 * j + (lane & 15)], acc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int n = n0 + 16 * j + (lane & 15);
+                if (n < p.N) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int64_t row = row0 + 2 * kq + h;
+                        if (row < p.nrows)
+                            p.store(row, n, make_float2(acc[j][2 * h], acc[j][2 * h + 1]));
+                    }
+                }
+            }
+        }
+    }
+}
+
+static size_t lds_bytes_rowgemm(int K, int nt)
+{
+    const int K4 = (K + 3) & ~3;
+    return (size_t)K4 * 16 * nt * sizeof(float) + (size_t)32 * (K4 + 1) * sizeof(float2);
+}
+
+// column tiles per pass: enough for N, and K x 16 NT floats <= 64 KB
+static int pick_nt(int K, int N)
+{
+    int nt = 1;
+    while (nt < 8 && 16 * nt < N) nt <<= 1;
+    while (nt > 1 && (size_t)K * 16 * nt * sizeof(float) > 65536) nt >>= 1;
+    return nt;
+}
+
+template <class P>
+static hipError_t launch_rowgemm(const P &p, hipStream_t s, int gridy = 1, int col0 = -1)
+{
+    if (p.nrows == 0) return hipSuccess;
+    if (p.K <= 128) {
+        int nt = 1;
+        while (nt < 8 && 16 * nt < p.N) nt <<= 1;
+        while (nt > 1 && lds_bytes_rowgemm(p.K, nt) > 65536) nt >>= 1;
+        const int64_t ntiles = (p.nrows + 31) / 32;
+        const unsigned gx = (unsigned)std::min<int64_t>(ntiles, 2048 / gridy + 1);
+        dim3 grid(gx, gridy), block(256);
+        const size_t lds = lds_bytes_rowgemm(p.K, nt);
+        switch (nt) {
+        case 1: hipLaunchKernelGGL((k_rowgemm_lds<P, 1>), grid, block, lds, s, p, col0); break;
+        case 2: hipLaunchKernelGGL((k_rowgemm_lds<P, 2>), grid, block, lds, s, p, col0); break;
+        case 4: hipLaunchKernelGGL((k_rowgemm_lds<P, 4>), grid, block, lds, s, p, col0); break;
+        default: hipLaunchKernelGGL((k_rowgemm_lds<P, 8>), grid, block, lds, s, p, col0); break;
+        }
+        return hipGetLastError();
+    }
+    const int64_t waves = (p.nrows + 7) / 8;
+    const int nt = pick_nt(p.K, p.N);
+    dim3 grid(waves_to_blocks(waves)), block(256);
+    const size_t lds = (size_t)p.K * 16 * nt * sizeof(float);
+    switch (nt) {
+    case 1: hipLaunchKernelGGL((k_rowgemm<P, 1>), grid, block, lds, s, p); break;
+    case 2: hipLaunchKernelGGL((k_rowgemm<P, 2>), grid, block, lds, s, p); break;
+    case 4: hipLaunchKernelGGL((k_rowgemm<P, 4>), grid, block, lds, s, p); break;
+    default: hipLaunchKernelGGL((k_rowgemm<P, 8>), grid, block, lds, s, p); break;
+    }
+    return hipGetLastError();
+}
+
+// M2M s3: one wave per (parent p, rhs r, block of 8 theta' rows, chunk of
+// 16*NT phi' columns); the 4 waves of a workgroup share the column chunk,
+// whose slice of the synthesis matrix G is staged in LDS.  The wave loops
+// over the children, multiplies each child's block by its shift and
+// accumulates the parent in registers.
+template <int NT>
+__global__ void __launch_bounds__(256)
+k_m2m_s3(const float2 *__restrict__ T2, const float *__restrict__ G,
+         const float2 *__restrict__ shift, const int32_t *__restrict__ child_start,
+         const uint8_t *__restrict__ child_oct, float2 *__restrict__ Sp, int64_t nboxp,
+         int R, int nthp, int nphp, int M)
+{
+    extern __shared__ float Gs[];
+    constexpr int NC = 16 * NT;
+    const int lane = threadIdx.x & 63;
+    const int nch = (nphp + NC - 1) / NC;
+    const int64_t blk = xcd_contiguous_i(blockIdx.x, gridDim.x);
+    const int chunk = (int)(blk % nch);
+    const int n0 = chunk * NC;
+    const int64_t wave = (blk / nch) * 4 + (threadIdx.x >> 6);
+    const int ntb = (nthp + 7) / 8;
+    for (int base = threadIdx.x; base < M * NC; base += 8 * blockDim.x) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int k = idx / NC, n = idx - (idx / NC) * NC;
+            v[u] = (idx < M * NC && n0 + n < nphp) ? G[k * nphp + n0 + n] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < M * NC) Gs[idx] = v[u];
+        }
+    }
+    __syncthreads();
+    if (wave >= nboxp * R * ntb) return;
+    const int tb = (int)(wave % ntb);
+    const int64_t pr = wave / ntb;
+    const int r = (int)(pr % R);
+    const int64_t p = pr / R;
+    const int64_t Kp = (int64_t)nthp * nphp;
+    const int t = (lane & 15) >> 1, part = lane & 1, kq = lane >> 4;
+    const int th_a = tb * 8 + t;
+    const bool rv = th_a < nthp;
+    const int c0 = child_start[p], c1 = child_start[p + 1];
+    float2 par[NT][2];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) par[j][0] = par[j][1] = make_float2(0.f, 0.f);
+    for (int c = c0; c < c1; ++c) {
+        const float2 *A = T2 + ((int64_t)c * R + r) * M * nthp + th_a;  // A[k * nthp]
+        floatx4 acc[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        int kb = 0;
+        for (; kb + 8 <= M; kb += 8) {
+            float av[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float2 x = rv ? A[(int64_t)(kb + 4 * u + kq) * nthp] : make_float2(0.f, 0.f);
+                av[u] = part ? x.y : x.x;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[j] = mfma4(av[u], Gs[(kb + 4 * u + kq) * NC + 16 * j + (lane & 15)], acc[j]);
+        }
+        for (; kb < M; kb += 4) {
+            const int k = kb + kq;
+            float av = 0.f;
+            if (rv && k < M) {
+                const float2 x = A[(int64_t)k * nthp];
+                av = part ? x.y : x.x;
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const float bv = k < M ? Gs[k * NC + 16 * j + (lane & 15)] : 0.f;
+                acc[j] = mfma4(av, bv, acc[j]);
+            }
+        }
+        const float2 *sh = shift + (int64_t)child_oct[c] * Kp;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int n = n0 + 16 * j + (lane & 15);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int th = tb * 8 + 2 * kq + h;
+                if (n < nphp && th < nthp) {
+                    const float2 sv = sh[(int64_t)th * nphp + n];
+                    const float yr = acc[j][2 * h], yi = acc[j][2 * h + 1];
+                    par[j][h].x += sv.x * yr - sv.y * yi;
+                    par[j][h].y += sv.x * yi + sv.y * yr;
+                }
+            }
+        }
+    }
+    float2 *out = Sp + (p * R + r) * Kp;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int n = n0 + 16 * j + (lane & 15);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int th = tb * 8 + 2 * kq + h;
+            if (n < nphp && th < nthp) out[(int64_t)th * nphp + n] = par[j][h];
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers --
+hipError_t interp_s1(const float2 *Sc, int64_t BR, int nthc, int nphc, const float *F, int M,
+                     float2 *T1, hipStream_t s)
+{
+    ProbS1 p{Sc, F, T1, BR * nthc, BR, nphc, M, nthc};
+    return launch_rowgemm(p, s);
+}
+
+hipError_t anterp_s1(const float2 *Lp, const int32_t *parent, const uint8_t *oct, int64_t nchild,
+                     int R, int nthp, int nphp, const float2 *shift, const float *F, int M,
+                     float2 *T1, hipStream_t s)
+{
+    ProbS1L p{Lp, shift, parent, oct, F, T1, nchild * R * nthp, nchild * R,
+              (int64_t)nthp * nphp, nphp, M, nthp, R};
+    return launch_rowgemm(p, s);
+}
+
+hipError_t theta_map(const float2 *T1, int64_t BR, int nin, int M, const float *mapsT, int nout,
+                     float2 *T2, hipStream_t s)
+{
+    if (BR == 0) return hipSuccess;
+    ProbS2 p{T1, mapsT, T2, BR, nin, nout, M, 0};
+    if (nin <= 128) return launch_rowgemm(p, s, M, 0);
+    const int64_t waves = (BR + 7) / 8;
+    dim3 grid(waves_to_blocks(waves), M), block(256);
+    const int nt = pick_nt(nin, nout);
+    const size_t lds = (size_t)nin * 16 * nt * sizeof(float);
+    switch (nt) {
+    case 1: hipLaunchKernelGGL((k_s2<1>), grid, block, lds, s, p); break;
+    case 2: hipLaunchKernelGGL((k_s2<2>), grid, block, lds, s, p); break;
+    case 4: hipLaunchKernelGGL((k_s2<4>), grid, block, lds, s, p); break;
+    default: hipLaunchKernelGGL((k_s2<8>), grid, block, lds, s, p); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M, const int32_t *child_start,
+                     const uint8_t *child_oct, const float2 *T2, const float *G,
+                     const float2 *shift, float2 *Sp, hipStream_t s)
+{
+    const int64_t waves = nboxp * R * ((nthp + 7) / 8);
+    if (waves == 0) return hipSuccess;
+    // widest column chunk that still gives >= 2048 waves (and fits 64 KB)
+    int nt = pick_nt(M, nphp);
+    while (nt > 1 && waves * ((nphp + 16 * nt - 1) / (16 * nt)) < 2048) nt >>= 1;
+    const int nch = (nphp + 16 * nt - 1) / (16 * nt);
+    dim3 grid((unsigned)(waves_to_blocks(waves) * nch)), block(256);
+    const size_t lds = (size_t)M * 16 * nt * sizeof(float);
+#define M2M_S3(NTV)                                                                        \
+    hipLaunchKernelGGL((k_m2m_s3<NTV>), grid, block, lds, s, T2, G, shift, child_start,    \
+                       child_oct, Sp, nboxp, R, nthp, nphp, M)
+    switch (nt) {
+    case 1: M2M_S3(1); break;
+    case 2: M2M_S3(2); break;
+    case 4: M2M_S3(4); break;
+    default: M2M_S3(8); break;
+    }
+#undef M2M_S3
+    return hipGetLastError();
+}
+
+hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M, const float2 *T2,
+                     const float *G, float2 *Lc, hipStream_t s)
+{
+    ProbS3L p{T2, G, Lc, nboxc * R * nthc, M, nphc, nthc};
+    return launch_rowgemm(p, s);
+}
+
+}  // namespace dev
+}  // namespace mlfma

@@ -16,20 +16,23 @@ hipError_t gather(const void *q, int dtype, const int32_t *perm, int64_t n,
 hipError_t zero(float2 *p, int64_t count, hipStream_t s);
 
 // near-field potential (field = 0) or gradient (field = 1) in sorted order:
-// out [n][R] or [n][R][3]
-hipError_t p2p(const float4 *pts, const int32_t *pt_leaf, const int32_t *pt_start,
-               const int32_t *near_start, const int32_t *near_idx,
-               const int32_t *leaf_coord, float leaf, float kw, const float2 *qs,
-               int64_t n, int R, int field, float2 *out, hipStream_t s);
+// out [n][R] or [n][R][3]; items[w] = (leaf, first target offset) covers up
+// to 64 targets of that leaf
+hipError_t p2p(const int2 *items, int64_t nitems, const float4 *pts,
+               const int32_t *pt_start, const int32_t *near_start, const int32_t *near_idx,
+               const int32_t *leaf_coord, float leaf, float kw, const float2 *qs, int R,
+               int field, float2 *out, hipStream_t s);
 
 // C2M: S[b][r][k] = sum_{j in b} q_j exp(-i kw khat_k . d_j)
 hipError_t c2m(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
                const float4 *khat_w, int64_t K, float kw, const float2 *qs,
                int R, float2 *S, hipStream_t s);
 
-// s1: out[row][col] = sum_j X[row][j] F[j][col]  (rows of length nin)
-hipError_t dft_rows(const float2 *X, int64_t rows, int nin, const float *F,
-                    int M, float2 *out, hipStream_t s);
+// Interpolation stages (interp.hip).  T1 layout [col][(box, rhs)][theta_in],
+// T2 layout [(box, rhs)][col][theta_out].
+// M2M s1: T1 = child spectra x F (phi DFT on the child grid)
+hipError_t interp_s1(const float2 *Sc, int64_t BR, int nthc, int nphc, const float *F,
+                     int M, float2 *T1, hipStream_t s);
 
 // L2L s1 with the shift fused: rows (child c, r, theta_p) of the parent's
 // local shifted by conj(shift[oct(c)])
@@ -38,9 +41,9 @@ hipError_t anterp_s1(const float2 *Lp, const int32_t *parent, const uint8_t *oct
                      const float2 *shift, const float *F, int M, float2 *out,
                      hipStream_t s);
 
-// s2: Yh[br][i'][col] = sum_i maps[m(col)][i'][i] Xh[br][i][col]
-hipError_t theta_map(const float2 *Xh, int64_t BR, int nin, int M,
-                     const float *maps, int nout, float2 *Yh, hipStream_t s);
+// s2: T2[br][col][i'] = sum_i mapsT[m(col)][i][i'] T1[col][br][i]
+hipError_t theta_map(const float2 *T1, int64_t BR, int nin, int M,
+                     const float *mapsT, int nout, float2 *T2, hipStream_t s);
 
 // M2M s3 + shift + aggregation (parent-centric, no atomics)
 hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M,
@@ -56,6 +59,27 @@ hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
 hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start,
                const int32_t *far_src, const int16_t *far_type, const float2 *T,
                const float2 *S, int R, float2 *Lout, hipStream_t s);
+
+// M2L by sibling groups with per-source records: rec_src[e] source box,
+// rec_off[8e + i] byte offset of the operator row of (child i of the parent,
+// source) in the LDS slice of 64 samples (row ntypes = zeros: no interaction)
+hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
+                   const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
+                   const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s);
+
+// M2L per observer with the operator slice in LDS
+hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start,
+                   const int32_t *far_src, const int16_t *far_type, const float2 *T,
+                   const float2 *S, int R, float2 *Lout, hipStream_t s);
+
+// M2L by sibling groups: parents at level l-1 (child ranges child_start),
+// their neighbour parents (CSR nbr_start/nbr_idx, Chebyshev 1, self
+// excluded), base = 49 cx + 7 cy + cz of the level-l boxes, typemap[343]
+// = operator index of an offset code or -1 (near / unused)
+hipError_t m2l_sg(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
+                  const int32_t *nbr_start, const int32_t *nbr_idx, const int32_t *base,
+                  const int16_t *typemap, const float2 *T, const float2 *S, int R,
+                  float2 *Lout, hipStream_t s);
 
 // L2O + near + scatter to caller order:
 // out[perm[s]][r] = near[s][r] + (i kw / 4 pi) sum_k w_k e^{i kw khat.d_s} L[b][r][k]

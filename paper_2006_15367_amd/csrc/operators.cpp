@@ -144,7 +144,8 @@ static void real_synthesis(int M, int nphi_out, std::vector<float> &G)
     }
 }
 
-// maps[m][i_to][i_from] = sum_{l=m}^{Lband} Pbar_l^m(x_to) Pbar_l^m(x_from) w_from
+// maps[m][i_from][i_to] = sum_{l=m}^{Lband} Pbar_l^m(x_to) Pbar_l^m(x_from) w_from
+// (stored with the input index first: it is the K index of the contraction)
 static void legendre_maps(int Lband, const std::vector<double> &xf, const std::vector<double> &wf,
                           const std::vector<double> &xt, std::vector<float> &maps)
 {
@@ -159,7 +160,7 @@ static void legendre_maps(int Lband, const std::vector<double> &xf, const std::v
                 double s = 0;
                 for (int l = m; l <= Lband; ++l)
                     s += Pt[(size_t)(l - m) * nt + a] * Pf[(size_t)(l - m) * nf + b];
-                maps[((size_t)m * nt + a) * nf + b] = (float)(s * wf[b]);
+                maps[((size_t)m * nf + b) * nt + a] = (float)(s * wf[b]);
             }
     });
 }

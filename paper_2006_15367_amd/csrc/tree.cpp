@@ -278,6 +278,27 @@ int build_tree(const double *xyz, int64_t n, double leaf, int max_levels,
     return MLFMA_OK;
 }
 
+void neighbour_lists(const Tree &t, int l, std::vector<int32_t> &start, std::vector<int32_t> &idx)
+{
+    const HostLevel &L = t.lev[l];
+    const int64_t side = (int64_t)1 << (l - 1);
+    start.assign(L.nbox + 1, 0);
+    idx.clear();
+    for (int64_t b = 0; b < L.nbox; ++b) {
+        const int32_t *c = &L.coord[3 * b];
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    if (!dx && !dy && !dz) continue;
+                    const int64_t x = c[0] + dx, y = c[1] + dy, z = c[2] + dz;
+                    if (x < 0 || y < 0 || z < 0 || x >= side || y >= side || z >= side) continue;
+                    const int64_t q = find_box(L, morton_key((uint32_t)x, (uint32_t)y, (uint32_t)z));
+                    if (q >= 0) idx.push_back((int32_t)q);
+                }
+        start[b + 1] = (int32_t)idx.size();
+    }
+}
+
 int update_positions(Tree *t, const double *xyz)
 {
     if (!t) return fail(MLFMA_EINVAL, "update_positions: tree is NULL");

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libmlfma.so")
 OK, EINVAL, EDEPTH, ENOMEM, EDEVICE, ERANGE = range(6)
 C64, C128 = 0, 1
 NEAR, FAR, CONJ = 1, 2, 4
-FP32, BF16X3_INTERP = 0, 1
+FP32, BF16X3_INTERP, NO_AUTOTUNE = 0, 1, 2
 KERNELS = ["gather", "p2p", "c2m", "interp_s1", "interp_s2", "interp_s3", "m2l",
            "anterp_s1", "anterp_s2", "anterp_s3", "l2o"]
 
@@ -80,6 +80,10 @@ EXPORTS = {
     "mlfma_set_device_memory_limit": ([ctypes.c_int64], None),
     "mlfma_profile_begin": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int64], ctypes.c_int),
     "mlfma_profile_end": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_ops_variants": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+                           ctypes.c_int),
+    "mlfma_ops_set_variant": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+                              ctypes.c_int),
     "mlfma_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "mlfma_last_error": ([], ctypes.c_char_p),
 }
@@ -222,10 +226,10 @@ class Operators:
     """Precomputed operators + device workspace (see
     mlfma_precompute_operators)."""
 
-    def __init__(self, tree, k, digits=3, max_rhs=1, bf16x3=False):
+    def __init__(self, tree, k, digits=3, max_rhs=1, bf16x3=False, autotune=True):
         lib = _load()
         h = ctypes.c_void_p()
-        flags = BF16X3_INTERP if bf16x3 else FP32
+        flags = (BF16X3_INTERP if bf16x3 else FP32) | (0 if autotune else NO_AUTOTUNE)
         _check(lib.mlfma_precompute_operators(tree.handle, float(k), int(digits),
                                               int(max_rhs), flags, ctypes.byref(h)),
                "mlfma_precompute_operators")
@@ -289,6 +293,18 @@ class Operators:
                                           out.data_ptr(), _stream_ptr(stream)),
                "mlfma_copy_spectra")
         return out
+
+    def variants(self, kernel="m2l"):
+        """Per-level kernel variant chosen by the autotuner (-1: no kernel)."""
+        nl = self.tree.info()["n_levels"]
+        out = np.empty(nl, np.int32)
+        _check(_load().mlfma_ops_variants(self._h, KERNELS.index(kernel), out.ctypes.data, nl),
+               "mlfma_ops_variants")
+        return out.tolist()
+
+    def set_variant(self, level, variant, kernel="m2l"):
+        _check(_load().mlfma_ops_set_variant(self._h, KERNELS.index(kernel), int(level),
+                                             int(variant)), "mlfma_ops_set_variant")
 
     def profile_begin(self, kernels=None, max_launches=4096):
         """Start HIP-event timing of the named kernels (default: all)."""

@@ -140,3 +140,20 @@ def test_field_vs_dense(c1):
     e = rel_l2(F, ref)
     say("field rel L2 vs dense", e)
     assert e < 1e-3
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_m2l_variant(c1, variant):
+    torch = c1["torch"]
+    say("c1: M2L variant", variant)
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    ops = c1["gops"]
+    chosen = ops.variants("m2l")
+    try:
+        for l in range(3, c1["ot"].n_lev + 1):
+            ops.set_variant(l, variant)
+        phi = _run(c1, ops.matvec, qd)
+    finally:
+        for l in range(3, c1["ot"].n_lev + 1):
+            ops.set_variant(l, chosen[l - 1])
+    assert rel_l2(phi, c1["ophi"]) < 1e-4
