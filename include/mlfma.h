@@ -199,6 +199,22 @@ int mlfma_matvec_ex(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs,
 int mlfma_field(mlfma_ops_t ops, const void *q, void *grad, int64_t nrhs,
                 int dtype, uint32_t parts, void *stream);
 
+/*
+ * Position gradient of a real loss through phi = A q (the chain rule of the
+ * pair sum, with the tree topology fixed):
+ *     out[i][a] = sum_c Re[ conj(g[i][c]) F_q(r_i)[c][a] + q[i][c] F_conj(g)(r_i)[c][a] ],
+ * where F_x is the field of charges x (mlfma_field) and g = 2 dL/d conj(phi)
+ * is the incoming gradient of phi (PyTorch's convention for complex
+ * tensors).  For L = ||phi - t||^2, g = 2 (phi - t) and
+ * out = 2 Re[conj(e) F_q + q F_conj(e)], e = phi - t.
+ *   q, g  device [n][nrhs] complex (dtype);  out device [n][3] real
+ *         (float for MLFMA_C64, double for MLFMA_C128), caller order
+ * Uses two field evaluations and the handle's workspace.  Errors as
+ * mlfma_matvec.
+ */
+int mlfma_position_gradient(mlfma_ops_t ops, const void *q, const void *g, void *out,
+                            int64_t nrhs, int dtype, void *stream);
+
 /* NULL is a no-op.  Wait for outstanding work on the handle's streams first. */
 void mlfma_destroy_ops(mlfma_ops_t ops);
 void mlfma_destroy_tree(mlfma_tree_t t);

@@ -68,6 +68,7 @@ struct mlfma_ops_s {
     int2 *p2p_items = nullptr;       // (leaf, first target) per 64-target chunk
     int64_t n_p2p_items = 0;
     float2 *qs = nullptr, *near = nullptr;
+    float2 *fq = nullptr, *fg = nullptr;  // fields for the position gradient [n][R][3]
     float2 *X1 = nullptr, *X2 = nullptr;
     int64_t scratch_elems = 0;
     uint64_t pos_version = 0;
@@ -300,8 +301,10 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s)
     return MLFMA_OK;
 }
 
+// conj_in/conj_out: -1 = follow MLFMA_CONJ in parts
 int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
-              uint32_t parts, int field, hipStream_t s)
+              uint32_t parts, int field, hipStream_t s, int conj_in = -1, int conj_out = -1,
+              int out_dtype = -1)
 {
     if (!o) return fail(MLFMA_EINVAL, "matvec: ops handle is NULL");
     if (nrhs < 1 || nrhs > o->max_rhs)
@@ -321,10 +324,13 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
     int rc = refresh_positions(o);
     const int R = (int)nrhs;
     const int conj = (parts & MLFMA_CONJ) ? 1 : 0;
+    const int cin = conj_in >= 0 ? conj_in : conj;
+    const int cout = conj_out >= 0 ? conj_out : conj;
+    const int odt = out_dtype >= 0 ? out_dtype : dtype;
     const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
     if (rc == MLFMA_OK) {
         rc = [&]() -> int {
-            LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, conj, o->qs, s));
+            LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, cin, o->qs, s));
             const int64_t nnear = o->n * R * (field ? 3 : 1);
             if (parts & MLFMA_NEAR)
                 LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->pts, o->pt_start,
@@ -340,7 +346,7 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
             DevLevel &leaf = o->lev[o->n_lev];
             LAUNCH(MLFMA_K_L2O, dev::l2o_scatter(o->pts, o->pt_leaf, o->perm, far ? leaf.khat_w : nullptr,
                                 far ? leaf.K : 0, (float)o->k, far ? leaf.Lloc : nullptr,
-                                o->near, o->n, R, field, far ? 1 : 0, conj, dtype, out, s));
+                                o->near, o->n, R, field, far ? 1 : 0, cout, odt, out, s));
             return MLFMA_OK;
         }();
     }
@@ -420,6 +426,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     pl.add((t->n / 64 + nleaf + 1) * 8);  // P2P work items
     pl.add(t->n * R * 8);              // qs
     pl.add(t->n * R * 8 * 3);          // near (3 components for the field)
+    pl.add(t->n * R * 8 * 3 * 2);      // two fields for the position gradient
     int64_t scratch = 0;
     if (nl >= 3) {
         for (int l = 3; l <= nl; ++l) {
@@ -481,6 +488,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         if ((r = upload(o, &o->p2p_items, items.data(), o->n_p2p_items))) return r;
         if ((r = dalloc(o, &o->qs, t->n * R))) return r;
         if ((r = dalloc(o, &o->near, t->n * R * 3))) return r;
+        if ((r = dalloc(o, &o->fq, t->n * R * 3))) return r;
+        if ((r = dalloc(o, &o->fg, t->n * R * 3))) return r;
         o->lev.resize(nl + 1);
         for (int l = 1; l <= nl; ++l) o->lev[l].nbox = t->lev[l].nbox;
         if (nl < 3) return MLFMA_OK;
@@ -623,6 +632,26 @@ int mlfma_field(mlfma_ops_t ops, const void *q, void *grad, int64_t nrhs, int dt
                 uint32_t parts, void *stream)
 {
     return do_matvec(ops, q, grad, nrhs, dtype, parts, 1, (hipStream_t)stream);
+}
+
+int mlfma_position_gradient(mlfma_ops_t o, const void *q, const void *g, void *out, int64_t nrhs,
+                            int dtype, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (!o) return fail(MLFMA_EINVAL, "position_gradient: ops is NULL");
+    if (o->n > 0 && (!q || !g || !out)) return fail(MLFMA_EINVAL, "position_gradient: null buffer");
+    // F_q and F_conj(g) into the workspace, both complex64 in caller order
+    int rc = do_matvec(o, q, o->fq, nrhs, dtype, 0, 1, s, 0, 0, MLFMA_C64);
+    if (rc) return rc;
+    rc = do_matvec(o, g, o->fg, nrhs, dtype, 0, 1, s, 1, 0, MLFMA_C64);
+    if (rc) return rc;
+    if (o->n == 0) return MLFMA_OK;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(MLFMA_EDEVICE, "hipGetDevice failed");
+    if (cur != o->device) (void)hipSetDevice(o->device);
+    hipError_t e = dev::position_grad_combine(q, g, dtype, o->fq, o->fg, o->n, (int)nrhs, out, s);
+    if (cur != o->device) (void)hipSetDevice(cur);
+    return check_hip(e, "position_grad_combine");
 }
 
 void mlfma_destroy_ops(mlfma_ops_t ops) { free_ops(ops); }

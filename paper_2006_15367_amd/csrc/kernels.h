@@ -55,6 +55,11 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M,
 hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
                      const float2 *Yh, const float *G, float2 *Lc, hipStream_t s);
 
+// out[i][a] = sum_r Re[conj(g[i][r]) Fq[i][r][a] + q[i][r] Fg[i][r][a]]
+// (q, g caller order, dtype 0 = complex64 / 1 = complex128; out float/double)
+hipError_t position_grad_combine(const void *q, const void *g, int dtype, const float2 *Fq,
+                                 const float2 *Fg, int64_t n, int R, void *out, hipStream_t s);
+
 // M2L: Lout[b][r][k] = sum_{e in far(b)} T[type_e][k] S[src_e][r][k]
 hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start,
                const int32_t *far_src, const int16_t *far_type, const float2 *T,

@@ -746,6 +746,43 @@ hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start, const int32_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------- position-gradient combine --
+template <typename Tc, typename Tr>
+__global__ void k_posgrad(const Tc *__restrict__ q, const Tc *__restrict__ g,
+                          const float2 *__restrict__ Fq, const float2 *__restrict__ Fg, int64_t n,
+                          int R, Tr *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float acc[3] = {0.f, 0.f, 0.f};
+    for (int r = 0; r < R; ++r) {
+        const Tc gv = g[i * R + r], qv = q[i * R + r];
+        const float gx = (float)gv.x, gy = (float)gv.y, qx = (float)qv.x, qy = (float)qv.y;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float2 f1 = Fq[(i * R + r) * 3 + a], f2 = Fg[(i * R + r) * 3 + a];
+            // Re(conj(g) f1) + Re(q f2)
+            acc[a] += gx * f1.x + gy * f1.y + qx * f2.x - qy * f2.y;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[i * 3 + a] = (Tr)acc[a];
+}
+
+hipError_t position_grad_combine(const void *q, const void *g, int dtype, const float2 *Fq,
+                                 const float2 *Fg, int64_t n, int R, void *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    dim3 grid(nblocks(n, 256)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_posgrad<float2, float>), grid, block, 0, s, (const float2 *)q,
+                           (const float2 *)g, Fq, Fg, n, R, (float *)out);
+    else
+        hipLaunchKernelGGL((k_posgrad<double2, double>), grid, block, 0, s, (const double2 *)q,
+                           (const double2 *)g, Fq, Fg, n, R, (double *)out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------ L2O + scatter --
 template <typename Tout, bool FIELD>
 __global__ void k_l2o_scatter(const float4 *__restrict__ pts,

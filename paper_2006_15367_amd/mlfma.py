@@ -63,6 +63,9 @@ EXPORTS = {
                          ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
     "mlfma_field": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                      ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_position_gradient": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p],
+                                ctypes.c_int),
     "mlfma_destroy_ops": ([ctypes.c_void_p], None),
     "mlfma_destroy_tree": ([ctypes.c_void_p], None),
     "mlfma_tree_info_get": ([ctypes.c_void_p, ctypes.POINTER(TreeInfo)], ctypes.c_int),
@@ -282,6 +285,20 @@ class Operators:
         q, out, nrhs = self._prep(q, comps=3)
         _check(_load().mlfma_field(self._h, q.data_ptr(), out.data_ptr(), nrhs,
                                    _dtype_code(q), parts, _stream_ptr(stream)), "mlfma_field")
+        return out
+
+    def position_gradient(self, q, g, stream=None):
+        """out[i, a] = sum_c Re[conj(g) F_q + q F_conj(g)] (see the C ABI)."""
+        import torch
+        q, _, nrhs = self._prep(q)
+        g = g.contiguous()
+        if g.shape != q.shape or g.dtype != q.dtype:
+            raise ValueError("g must match q in shape and dtype")
+        rdt = torch.float32 if q.dtype == torch.complex64 else torch.float64
+        out = torch.empty((self.n, 3), dtype=rdt, device=q.device)
+        _check(_load().mlfma_position_gradient(self._h, q.data_ptr(), g.data_ptr(),
+                                               out.data_ptr(), nrhs, _dtype_code(q),
+                                               _stream_ptr(stream)), "mlfma_position_gradient")
         return out
 
     def copy_spectra(self, level, which, nrhs=1, stream=None):
