@@ -277,12 +277,13 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s)
     const int nl = o->n_lev;
     DevLevel &leaf = o->lev[nl];
     const float kw = (float)o->k;
+    const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
     LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
-        LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s));
-        LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s));
+        LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s, b3));
+        LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s, b3));
         LAUNCH(MLFMA_K_INTERP_S3, dev::interp_s3(P.nbox, R, P.nth, P.nph, M, P.child_start, C.oct, o->X2, P.iG,
                           P.shift, P.S, s));
     }
@@ -294,9 +295,9 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s)
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
         LAUNCH(MLFMA_K_ANTERP_S1, dev::anterp_s1(P.Lloc, C.parent, C.oct, C.nbox, R, P.nth, P.nph, P.shift, P.aF, M,
-                          o->X1, s));
-        LAUNCH(MLFMA_K_ANTERP_S2, dev::theta_map(o->X1, C.nbox * R, P.nth, M, P.aB, C.nth, o->X2, s));
-        LAUNCH(MLFMA_K_ANTERP_S3, dev::anterp_s3(C.nbox, R, C.nth, C.nph, M, o->X2, P.aG, C.Lloc, s));
+                          o->X1, s, b3));
+        LAUNCH(MLFMA_K_ANTERP_S2, dev::theta_map(o->X1, C.nbox * R, P.nth, M, P.aB, C.nth, o->X2, s, b3));
+        LAUNCH(MLFMA_K_ANTERP_S3, dev::anterp_s3(C.nbox, R, C.nth, C.nph, M, o->X2, P.aG, C.Lloc, s, b3));
     }
     return MLFMA_OK;
 }

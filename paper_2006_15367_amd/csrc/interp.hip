@@ -346,6 +346,148 @@ __global__ void __launch_bounds__(256) k_rowgemm_lds(P p, int col_override)
     }
 }
 
+// ------------------------------------------------ BF16 split precision --
+// The same contraction with each FP32 operand split x = hi + lo, hi =
+// bf16(x), lo = bf16(x - hi), and the product taken as hi*hi + hi*lo +
+// lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (relative error
+// about 2^-16).  Lane l feeds A[l%16][8(l/16) .. 8(l/16)+7] and
+// B[8(l/16) .. +7][l%16] and receives the same D layout as the FP32 path.
+// LDS holds the data tile as hi/lo planes [32 rows x 2 parts][K32] and the
+// operator as hi/lo planes [NC][K32] (transposed), so every fragment is one
+// 16-byte LDS read.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits_rn(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short b)
+{
+    return __uint_as_float((unsigned)b << 16);
+}
+__device__ __forceinline__ void split_bf16(float x, unsigned short &hi, unsigned short &lo)
+{
+    hi = bf16_bits_rn(x);
+    lo = bf16_bits_rn(x - bf16_bits_to_float(hi));
+}
+
+template <class P, int NT>
+__global__ void __launch_bounds__(256) k_rowgemm_bf16x3(P p, int col_override)
+{
+    extern __shared__ unsigned short sm16[];
+    constexpr int NC = 16 * NT;
+    const int K = p.K;
+    const int K32 = (K + 31) & ~31;
+    const int KP = K32 + 8;                       // row pitch (bf16): +16 B spreads banks
+    unsigned short *Bh = sm16;                    // [NC][KP]
+    unsigned short *Bl = Bh + NC * KP;
+    unsigned short *Ah = Bl + NC * KP;            // [64][KP]: row 2t+part
+    unsigned short *Al = Ah + 64 * KP;
+    if (col_override >= 0) p.set_col(col_override + blockIdx.y);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, i16 = lane & 15;
+    const int64_t ntiles = (p.nrows + 31) / 32;
+    for (int n0 = 0; n0 < p.N; n0 += NC) {
+        __syncthreads();
+        for (int base = threadIdx.x; base < K32 * NC; base += 4 * blockDim.x) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = base + u * blockDim.x;
+                const int n = idx / K32, k = idx - (idx / K32) * K32;
+                v[u] = (idx < K32 * NC && k < K && n0 + n < p.N) ? p.b(k, n0 + n) : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = base + u * blockDim.x;
+                if (idx < K32 * NC) {
+                    const int n = idx / K32, k = idx - (idx / K32) * K32;
+                    unsigned short h, l;
+                    split_bf16(v[u], h, l);
+                    Bh[n * KP + k] = h;
+                    Bl[n * KP + k] = l;
+                }
+            }
+        }
+        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int64_t rbase = tile * 32;
+            __syncthreads();
+            for (int base = threadIdx.x; base < 32 * K32; base += 4 * blockDim.x) {
+                float2 v[4];
+                int rl_[4], k_[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = base + u * blockDim.x;
+                    int rl, k;
+                    if (P::rows_fast) {
+                        k = idx >> 5;
+                        rl = idx & 31;
+                    } else {
+                        rl = idx / K32;
+                        k = idx - rl * K32;
+                    }
+                    rl_[u] = idx < 32 * K32 ? rl : -1;
+                    k_[u] = k;
+                    const int64_t row = rbase + rl;
+                    v[u] = (rl_[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
+                                                                    : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (rl_[u] < 0) continue;
+                    unsigned short h, l;
+                    split_bf16(v[u].x, h, l);
+                    Ah[(2 * rl_[u]) * KP + k_[u]] = h;
+                    Al[(2 * rl_[u]) * KP + k_[u]] = l;
+                    split_bf16(v[u].y, h, l);
+                    Ah[(2 * rl_[u] + 1) * KP + k_[u]] = h;
+                    Al[(2 * rl_[u] + 1) * KP + k_[u]] = l;
+                }
+            }
+            __syncthreads();
+            const int64_t row0 = rbase + wave * 8;
+            if (row0 >= p.nrows) continue;
+            const int arow = wave * 16 + i16;     // real row 2t+part of this wave
+            floatx4 acc[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int kb = 0; kb < K32; kb += 32) {
+                const int kk = kb + 8 * kq;
+                const bf16x8 ah = *(const bf16x8 *)(Ah + arow * KP + kk);
+                const bf16x8 al = *(const bf16x8 *)(Al + arow * KP + kk);
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const int n = 16 * j + i16;
+                    const bf16x8 bh = *(const bf16x8 *)(Bh + n * KP + kk);
+                    const bf16x8 bl = *(const bf16x8 *)(Bl + n * KP + kk);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int n = n0 + 16 * j + i16;
+                if (n < p.N) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int64_t row = row0 + 2 * kq + h;
+                        if (row < p.nrows)
+                            p.store(row, n, make_float2(acc[j][2 * h], acc[j][2 * h + 1]));
+                    }
+                }
+            }
+        }
+    }
+}
+
+static size_t lds_bytes_bf16x3(int K, int nt)
+{
+    const int KP = ((K + 31) & ~31) + 8;
+    return (size_t)(2 * 16 * nt * KP + 2 * 64 * KP) * sizeof(unsigned short);
+}
+
 static size_t lds_bytes_rowgemm(int K, int nt)
 {
     const int K4 = (K + 3) & ~3;
@@ -362,9 +504,26 @@ static int pick_nt(int K, int N)
 }
 
 template <class P>
-static hipError_t launch_rowgemm(const P &p, hipStream_t s, int gridy = 1, int col0 = -1)
+static hipError_t launch_rowgemm(const P &p, hipStream_t s, int gridy = 1, int col0 = -1,
+                                 bool bf16x3 = false)
 {
     if (p.nrows == 0) return hipSuccess;
+    if (bf16x3 && p.K <= 256) {
+        int nt = 1;
+        while (nt < 8 && 16 * nt < p.N) nt <<= 1;
+        while (nt > 1 && lds_bytes_bf16x3(p.K, nt) > 81920) nt >>= 1;
+        const int64_t ntiles = (p.nrows + 31) / 32;
+        const unsigned gx = (unsigned)std::min<int64_t>(ntiles, 2048 / gridy + 1);
+        dim3 grid(gx, gridy), block(256);
+        const size_t lds = lds_bytes_bf16x3(p.K, nt);
+        switch (nt) {
+        case 1: hipLaunchKernelGGL((k_rowgemm_bf16x3<P, 1>), grid, block, lds, s, p, col0); break;
+        case 2: hipLaunchKernelGGL((k_rowgemm_bf16x3<P, 2>), grid, block, lds, s, p, col0); break;
+        case 4: hipLaunchKernelGGL((k_rowgemm_bf16x3<P, 4>), grid, block, lds, s, p, col0); break;
+        default: hipLaunchKernelGGL((k_rowgemm_bf16x3<P, 8>), grid, block, lds, s, p, col0); break;
+        }
+        return hipGetLastError();
+    }
     if (p.K <= 128) {
         int nt = 1;
         while (nt < 8 && 16 * nt < p.N) nt <<= 1;
@@ -505,27 +664,27 @@ k_m2m_s3(const float2 *__restrict__ T2, const float *__restrict__ G,
 
 // ------------------------------------------------------------ launchers --
 hipError_t interp_s1(const float2 *Sc, int64_t BR, int nthc, int nphc, const float *F, int M,
-                     float2 *T1, hipStream_t s)
+                     float2 *T1, hipStream_t s, bool bf16x3)
 {
     ProbS1 p{Sc, F, T1, BR * nthc, BR, nphc, M, nthc};
-    return launch_rowgemm(p, s);
+    return launch_rowgemm(p, s, 1, -1, bf16x3);
 }
 
 hipError_t anterp_s1(const float2 *Lp, const int32_t *parent, const uint8_t *oct, int64_t nchild,
                      int R, int nthp, int nphp, const float2 *shift, const float *F, int M,
-                     float2 *T1, hipStream_t s)
+                     float2 *T1, hipStream_t s, bool bf16x3)
 {
     ProbS1L p{Lp, shift, parent, oct, F, T1, nchild * R * nthp, nchild * R,
               (int64_t)nthp * nphp, nphp, M, nthp, R};
-    return launch_rowgemm(p, s);
+    return launch_rowgemm(p, s, 1, -1, bf16x3);
 }
 
 hipError_t theta_map(const float2 *T1, int64_t BR, int nin, int M, const float *mapsT, int nout,
-                     float2 *T2, hipStream_t s)
+                     float2 *T2, hipStream_t s, bool bf16x3)
 {
     if (BR == 0) return hipSuccess;
     ProbS2 p{T1, mapsT, T2, BR, nin, nout, M, 0};
-    if (nin <= 128) return launch_rowgemm(p, s, M, 0);
+    if (nin <= 128 || (bf16x3 && nin <= 256)) return launch_rowgemm(p, s, M, 0, bf16x3);
     const int64_t waves = (BR + 7) / 8;
     dim3 grid(waves_to_blocks(waves), M), block(256);
     const int nt = pick_nt(nin, nout);
@@ -565,10 +724,10 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M, const int3
 }
 
 hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M, const float2 *T2,
-                     const float *G, float2 *Lc, hipStream_t s)
+                     const float *G, float2 *Lc, hipStream_t s, bool bf16x3)
 {
     ProbS3L p{T2, G, Lc, nboxc * R * nthc, M, nphc, nthc};
-    return launch_rowgemm(p, s);
+    return launch_rowgemm(p, s, 1, -1, bf16x3);
 }
 
 }  // namespace dev

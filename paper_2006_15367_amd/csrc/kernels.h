@@ -31,19 +31,20 @@ hipError_t c2m(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
 // Interpolation stages (interp.hip).  T1 layout [col][(box, rhs)][theta_in],
 // T2 layout [(box, rhs)][col][theta_out].
 // M2M s1: T1 = child spectra x F (phi DFT on the child grid)
+// (bf16x3: the BF16 split-precision MFMA path; FP32 MFMA otherwise)
 hipError_t interp_s1(const float2 *Sc, int64_t BR, int nthc, int nphc, const float *F,
-                     int M, float2 *T1, hipStream_t s);
+                     int M, float2 *T1, hipStream_t s, bool bf16x3);
 
 // L2L s1 with the shift fused: rows (child c, r, theta_p) of the parent's
 // local shifted by conj(shift[oct(c)])
 hipError_t anterp_s1(const float2 *Lp, const int32_t *parent, const uint8_t *oct,
                      int64_t nchild, int R, int nthp, int nphp,
                      const float2 *shift, const float *F, int M, float2 *out,
-                     hipStream_t s);
+                     hipStream_t s, bool bf16x3);
 
 // s2: T2[br][col][i'] = sum_i mapsT[m(col)][i][i'] T1[col][br][i]
 hipError_t theta_map(const float2 *T1, int64_t BR, int nin, int M,
-                     const float *mapsT, int nout, float2 *T2, hipStream_t s);
+                     const float *mapsT, int nout, float2 *T2, hipStream_t s, bool bf16x3);
 
 // M2M s3 + shift + aggregation (parent-centric, no atomics)
 hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M,
@@ -53,7 +54,7 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M,
 
 // L2L s3 + add into the child's local expansion
 hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
-                     const float2 *Yh, const float *G, float2 *Lc, hipStream_t s);
+                     const float2 *Yh, const float *G, float2 *Lc, hipStream_t s, bool bf16x3);
 
 // out[i][a] = sum_r Re[conj(g[i][r]) Fq[i][r][a] + q[i][r] Fg[i][r][a]]
 // (q, g caller order, dtype 0 = complex64 / 1 = complex128; out float/double)

@@ -223,14 +223,15 @@ hipError_t p2p(const int2 *items, int64_t nitems, const float4 *pts, const int32
                hipStream_t s)
 {
     if (nitems == 0) return hipSuccess;
-    if (R == 1)
-        return p2p_rc<1>(items, nitems, pts, pt_start, near_start, near_idx, coord, leaf, kw,
-                         qs, R, field, out, s);
-    if (R == 2)
-        return p2p_rc<2>(items, nitems, pts, pt_start, near_start, near_idx, coord, leaf, kw,
-                         qs, R, field, out, s);
-    return p2p_rc<4>(items, nitems, pts, pt_start, near_start, near_idx, coord, leaf, kw, qs,
-                     R, field, out, s);
+#define P2P_RC(RCV) \
+    return p2p_rc<RCV>(items, nitems, pts, pt_start, near_start, near_idx, coord, leaf, kw, qs, \
+                       R, field, out, s)
+    if (R == 1) P2P_RC(1);
+    if (R == 2) P2P_RC(2);
+    if (R <= 4) P2P_RC(4);
+    if (R <= 8 || field) P2P_RC(8);
+    P2P_RC(16);
+#undef P2P_RC
 }
 
 // ------------------------------------------------------------------- C2M --
@@ -292,8 +293,11 @@ hipError_t c2m(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
     if (R == 1) {
         hipLaunchKernelGGL(k_c2m<1>, dim3((unsigned)nleaf, 1), dim3(256), 0, s, pts, pt_start,
                            khat_w, K, kw, qs, R, S);
+    } else if (R <= 4) {
+        hipLaunchKernelGGL(k_c2m<4>, dim3((unsigned)nleaf, 1), dim3(256), 0, s, pts,
+                           pt_start, khat_w, K, kw, qs, R, S);
     } else {
-        hipLaunchKernelGGL(k_c2m<4>, dim3((unsigned)nleaf, (R + 3) / 4), dim3(256), 0, s, pts,
+        hipLaunchKernelGGL(k_c2m<16>, dim3((unsigned)nleaf, (R + 15) / 16), dim3(256), 0, s, pts,
                            pt_start, khat_w, K, kw, qs, R, S);
     }
     return hipGetLastError();
@@ -784,7 +788,7 @@ hipError_t position_grad_combine(const void *q, const void *g, int dtype, const 
 }
 
 // ------------------------------------------------------ L2O + scatter --
-template <typename Tout, bool FIELD>
+template <typename Tout, bool FIELD, int RC>
 __global__ void k_l2o_scatter(const float4 *__restrict__ pts,
                               const int32_t *__restrict__ pt_leaf,
                               const int32_t *__restrict__ perm,
@@ -792,68 +796,87 @@ __global__ void k_l2o_scatter(const float4 *__restrict__ pts,
                               const float2 *__restrict__ L, const float2 *__restrict__ near,
                               int64_t n, int R, int far, int conj_out, Tout *__restrict__ out)
 {
+    // one thread per (point, chunk of RC right-hand sides): the plane-wave
+    // factor of each sample is computed once and used for the whole chunk
     constexpr int NA = FIELD ? 3 : 1;
+    const int nch = (R + RC - 1) / RC;
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * R) return;
-    const int64_t s = idx / R;
-    const int r = (int)(idx - s * R);
-    float2 acc[NA];
+    if (idx >= n * nch) return;
+    const int64_t s = idx / nch;
+    const int r0 = (int)(idx - s * nch) * RC;
+    const int rc = min(RC, R - r0);
+    float2 acc[RC][NA];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = make_float2(0.f, 0.f);
+    for (int c = 0; c < RC; ++c)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[c][a] = make_float2(0.f, 0.f);
     if (far) {
         const float4 d = pts[s];
-        const float2 *Lb = L + ((int64_t)pt_leaf[s] * R + r) * K;
+        const float2 *Lb = L + ((int64_t)pt_leaf[s] * R + r0) * K;
         for (int64_t k = 0; k < K; ++k) {
             const float4 kh = khat_w[k];
             float sn, cs;
             __sincosf(kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
             const float2 e = make_float2(cs * kh.w, sn * kh.w);
-            const float2 v = cmul(e, Lb[k]);
-            if (FIELD) {
-                acc[0].x = fmaf(v.x, kh.x, acc[0].x);
-                acc[0].y = fmaf(v.y, kh.x, acc[0].y);
-                acc[FIELD ? 1 : 0].x = fmaf(v.x, kh.y, acc[FIELD ? 1 : 0].x);
-                acc[FIELD ? 1 : 0].y = fmaf(v.y, kh.y, acc[FIELD ? 1 : 0].y);
-                acc[FIELD ? 2 : 0].x = fmaf(v.x, kh.z, acc[FIELD ? 2 : 0].x);
-                acc[FIELD ? 2 : 0].y = fmaf(v.y, kh.z, acc[FIELD ? 2 : 0].y);
-            } else {
-                acc[0].x += v.x;
-                acc[0].y += v.y;
+#pragma unroll
+            for (int c = 0; c < RC; ++c) {
+                if (c < rc) {
+                    const float2 v = cmul(e, Lb[c * K + k]);
+                    if (FIELD) {
+                        const float kd[3] = {kh.x, kh.y, kh.z};
+#pragma unroll
+                        for (int a = 0; a < NA; ++a) {
+                            acc[c][a].x = fmaf(v.x, kd[a], acc[c][a].x);
+                            acc[c][a].y = fmaf(v.y, kd[a], acc[c][a].y);
+                        }
+                    } else {
+                        acc[c][0].x += v.x;
+                        acc[c][0].y += v.y;
+                    }
+                }
             }
         }
         // potential: (i kw / 4pi) acc;  gradient: (i kw)^2 / 4pi = -kw^2/4pi
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            if (FIELD) {
-                const float sc = -kw * kw * kInv4Pi;
-                acc[a] = make_float2(sc * acc[a].x, sc * acc[a].y);
-            } else {
-                const float sc = kw * kInv4Pi;
-                acc[a] = make_float2(-sc * acc[a].y, sc * acc[a].x);
+        for (int c = 0; c < RC; ++c)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                if (FIELD) {
+                    const float sc = -kw * kw * kInv4Pi;
+                    acc[c][a] = make_float2(sc * acc[c][a].x, sc * acc[c][a].y);
+                } else {
+                    const float sc = kw * kInv4Pi;
+                    acc[c][a] = make_float2(-sc * acc[c][a].y, sc * acc[c][a].x);
+                }
+            }
+    }
+    const int64_t o = (int64_t)perm[s] * R;
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+        if (c < rc) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                float2 v = near[((s * R) + r0 + c) * NA + a];
+                v.x += acc[c][a].x;
+                v.y += acc[c][a].y;
+                if (conj_out) v.y = -v.y;
+                out[(o + r0 + c) * NA + a].x = v.x;
+                out[(o + r0 + c) * NA + a].y = v.y;
             }
         }
     }
-    const int64_t o = (int64_t)perm[s] * R + r;
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        float2 v = near[idx * NA + a];
-        v.x += acc[a].x;
-        v.y += acc[a].y;
-        if (conj_out) v.y = -v.y;
-        out[o * NA + a].x = v.x;
-        out[o * NA + a].y = v.y;
-    }
 }
 
-hipError_t l2o_scatter(const float4 *pts, const int32_t *pt_leaf, const int32_t *perm,
-                       const float4 *khat_w, int64_t K, float kw, const float2 *L,
-                       const float2 *near, int64_t n, int R, int field, int far, int conj_out,
-                       int dtype, void *out, hipStream_t s)
+template <int RC>
+static hipError_t l2o_rc(const float4 *pts, const int32_t *pt_leaf, const int32_t *perm,
+                         const float4 *khat_w, int64_t K, float kw, const float2 *L,
+                         const float2 *near, int64_t n, int R, int field, int far, int conj_out,
+                         int dtype, void *out, hipStream_t s)
 {
-    if (n * R == 0) return hipSuccess;
-    dim3 grid(nblocks(n * R, 256)), block(256);
-#define L2O_LAUNCH(T, F)                                                                 \
-    hipLaunchKernelGGL((k_l2o_scatter<T, F>), grid, block, 0, s, pts, pt_leaf, perm, khat_w, \
+    const int64_t total = n * ((R + RC - 1) / RC);
+    dim3 grid(nblocks(total, 256)), block(256);
+#define L2O_LAUNCH(T, F)                                                                       \
+    hipLaunchKernelGGL((k_l2o_scatter<T, F, RC>), grid, block, 0, s, pts, pt_leaf, perm, khat_w, \
                        K, kw, L, near, n, R, far, conj_out, (T *)out)
     if (dtype == 0) {
         if (field) L2O_LAUNCH(float2, true); else L2O_LAUNCH(float2, false);
@@ -862,6 +885,22 @@ hipError_t l2o_scatter(const float4 *pts, const int32_t *pt_leaf, const int32_t 
     }
 #undef L2O_LAUNCH
     return hipGetLastError();
+}
+
+hipError_t l2o_scatter(const float4 *pts, const int32_t *pt_leaf, const int32_t *perm,
+                       const float4 *khat_w, int64_t K, float kw, const float2 *L,
+                       const float2 *near, int64_t n, int R, int field, int far, int conj_out,
+                       int dtype, void *out, hipStream_t s)
+{
+    if (n * R == 0) return hipSuccess;
+    if (R == 1)
+        return l2o_rc<1>(pts, pt_leaf, perm, khat_w, K, kw, L, near, n, R, field, far, conj_out,
+                         dtype, out, s);
+    if (R <= 4 || field)
+        return l2o_rc<4>(pts, pt_leaf, perm, khat_w, K, kw, L, near, n, R, field, far, conj_out,
+                         dtype, out, s);
+    return l2o_rc<16>(pts, pt_leaf, perm, khat_w, K, kw, L, near, n, R, field, far, conj_out,
+                      dtype, out, s);
 }
 
 }  // namespace dev

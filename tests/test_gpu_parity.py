@@ -157,3 +157,42 @@ def test_every_m2l_variant(c1, variant):
         for l in range(3, c1["ot"].n_lev + 1):
             ops.set_variant(l, chosen[l - 1])
     assert rel_l2(phi, c1["ophi"]) < 1e-4
+
+
+def test_bf16x3_interpolation_accuracy(c1):
+    """BF16 split-precision interpolation: same accuracy class as FP32."""
+    torch = c1["torch"]
+    G = c1["G"]
+    say("c1: bf16x3 operators")
+    ops = G.Operators(c1["gt"], K, W.DIGITS, max_rhs=1, bf16x3=True)
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    phi = _run(c1, ops.matvec, qd)
+    e_orc = rel_l2(phi, c1["ophi"])
+    e_dense = rel_l2(phi, c1["dense"])
+    fp32 = _run(c1, c1["gops"].matvec, qd)
+    say("bf16x3 rel L2 vs FP64 MLFMA", e_orc, "vs dense", e_dense, "vs FP32 path",
+        rel_l2(phi, fp32))
+    assert e_dense < 1e-3
+    assert e_orc < 2e-4
+    assert rel_l2(phi, fp32) < 2e-4
+
+
+def test_batched_64_rhs_equals_single():
+    """64 right-hand sides in one call equal 64 single-RHS calls."""
+    torch = cuda_or_skip()
+    from paper_2006_15367_amd import mlfma as G
+    xyz, Q = W.make("sphere262k_r64", n=32768)
+    say("batched: 32768-point sphere, 64 RHS")
+    tree = G.Tree(xyz, W.LEAF_SIZE)
+    ops = G.Operators(tree, K, W.DIGITS, max_rhs=64)
+    P = ops.matvec(torch.from_numpy(Q).cuda())
+    A = ops.adjoint(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    P = P.cpu().numpy()
+    A = A.cpu().numpy()
+    for r in (0, 17, 63):
+        p = ops.matvec(torch.from_numpy(np.ascontiguousarray(Q[:, r])).cuda())
+        a = ops.adjoint(torch.from_numpy(np.ascontiguousarray(Q[:, r])).cuda())
+        torch.cuda.synchronize()
+        assert rel_l2(P[:, r], p.cpu().numpy()) < 1e-6
+        assert rel_l2(A[:, r], a.cpu().numpy()) < 1e-6
