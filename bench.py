@@ -32,9 +32,9 @@ PEAK_FP32_TFLOPS = 157.3        # FP32 vector and FP32 matrix
 PEAK_BF16_TFLOPS = 2500.0       # dense BF16 MFMA
 
 # bound of each kernel as implemented
-BOUND = {"gather": "hbm", "p2p": "alu", "c2m": "alu", "interp_s1": "alu",
-         "interp_s2": "alu", "interp_s3": "alu", "m2l": "hbm", "anterp_s1": "alu",
-         "anterp_s2": "alu", "anterp_s3": "alu", "l2o": "alu"}
+BOUND = {"gather": "hbm", "p2p": "alu", "c2m": "alu", "interp_s1": "mfma",
+         "interp_s2": "mfma", "interp_s3": "mfma", "m2l": "alu", "anterp_s1": "mfma",
+         "anterp_s2": "mfma", "anterp_s3": "mfma", "l2o": "alu"}
 
 
 def algorithmic_work(tinfo, levels, R):
@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--workload", default="sphere262k")
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--bf16x3", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the matvec into a HIP graph and replay it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
@@ -156,7 +158,8 @@ def main():
     t0 = time.perf_counter()
     tree = G.Tree(xyz, W.LEAF_SIZE)
     t1 = time.perf_counter()
-    ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=args.bf16x3)
+    ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=args.bf16x3,
+                      graph=args.graph)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     tinfo = tree.info()
@@ -170,37 +173,51 @@ def main():
         dst = src.clone()
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        phi = ops.matvec(qd)
-    torch.cuda.synchronize()
-    # one profiled step picks the dominant kernel
-    ops.profile_begin(None, 4096)
-    ops.matvec(qd)
-    torch.cuda.synchronize()
-    per_kernel = ops.profile_end()
-    dominant = max(per_kernel, key=lambda k: per_kernel[k][0])
-    launches = per_kernel[dominant][1]
+    # graph mode replays a captured graph, which needs a non-null stream
+    st = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    with torch.cuda.stream(st):
+        for _ in range(args.warmup):
+            phi = ops.matvec(qd, stream=st)
+        torch.cuda.synchronize()
+        # one profiled (eager) step picks the dominant kernel
+        ops.profile_begin(None, 4096)
+        ops.matvec(qd, stream=st)
+        torch.cuda.synchronize()
+        per_kernel = ops.profile_end()
+        dominant = max(per_kernel, key=lambda k: per_kernel[k][0])
+        launches = per_kernel[dominant][1]
 
-    # timed region: K steps; HIP events bracket the dominant kernel's launches
-    ops.profile_begin([dominant], launches * args.steps + 16)
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    for _ in range(args.steps):
-        phi = ops.matvec(qd)
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    dom = ops.profile_end()[dominant]
-    ms_per_step = (te - ts) * 1e3 / args.steps
+        # timed region: K steps.  Eager mode brackets the dominant kernel's
+        # launches with HIP events inside the timed region; graph mode times
+        # them in an equal number of eager steps right after it.
+        if not args.graph:
+            ops.profile_begin([dominant], launches * args.steps + 16)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            phi = ops.matvec(qd, stream=st)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        eager_ms = None
+        if args.graph:
+            ops.profile_begin([dominant], launches * args.steps + 16)
+            te0 = time.perf_counter()
+            for _ in range(args.steps):
+                ops.matvec(qd, stream=st)
+            torch.cuda.synchronize()
+            eager_ms = (time.perf_counter() - te0) * 1e3 / args.steps
+        dom = ops.profile_end()[dominant]
+        ms_per_step = (te - ts) * 1e3 / args.steps
 
-    # adjoint, timed the same way (no events)
-    for _ in range(2):
-        ops.adjoint(vd)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    for _ in range(args.steps):
-        psi = ops.adjoint(vd)
-    torch.cuda.synchronize()
-    adj_ms = (time.perf_counter() - ta) * 1e3 / args.steps
+        # adjoint, timed the same way (no events)
+        for _ in range(2):
+            ops.adjoint(vd, stream=st)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            psi = ops.adjoint(vd, stream=st)
+        torch.cuda.synchronize()
+        adj_ms = (time.perf_counter() - ta) * 1e3 / args.steps
 
     work = algorithmic_work(tinfo, levels, R)
     rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
@@ -218,6 +235,8 @@ def main():
         "adjoint": {"value": round(xyz.shape[0] * R / (adj_ms * 1e-3), 1),
                     "ms_per_step": round(adj_ms, 4)},
         "setup_s": {"tree": round(t1 - t0, 3), "operators": round(t2 - t1, 3)},
+        "graph": bool(args.graph),
+        "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
         "m2l_variant_per_level": ops.variants("m2l"),
         "roofline": rl,

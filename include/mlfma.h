@@ -70,8 +70,12 @@ enum mlfma_flags {
     MLFMA_FP32 = 0,          /* FP32 interpolation / anterpolation GEMMs     */
     MLFMA_BF16X3_INTERP = 1, /* interpolation GEMMs in BF16 split precision
                                 (hi*hi + hi*lo + lo*hi, FP32 accumulation)  */
-    MLFMA_NO_AUTOTUNE = 2    /* skip the kernel-variant timing at precompute
+    MLFMA_NO_AUTOTUNE = 2,   /* skip the kernel-variant timing at precompute
                                 (variants differ only in summation order)   */
+    MLFMA_USE_GRAPH = 4      /* capture each distinct call (buffers, nrhs,
+                                dtype, parts, stream) into a HIP graph once
+                                and replay it afterwards; calls on the null
+                                stream and profiled calls run eagerly       */
 };
 
 typedef struct mlfma_tree_info {

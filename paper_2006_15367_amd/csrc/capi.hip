@@ -74,6 +74,19 @@ struct mlfma_ops_s {
     uint64_t pos_version = 0;
     std::vector<void *> allocs;
     int64_t last_R = 0;
+    // captured graphs of previous calls (MLFMA_USE_GRAPH)
+    struct GraphEntry {
+        const void *q = nullptr;
+        void *out = nullptr;
+        int64_t nrhs = 0;
+        int dtype = 0, field = 0, cin = 0, cout = 0, odt = 0;
+        uint32_t parts = 0;
+        hipStream_t stream = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint64_t use = 0;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     // launch timing (diagnostics)
     uint32_t prof_mask = 0;
     int64_t prof_cap = 0, prof_used = 0;
@@ -156,10 +169,18 @@ int upload(mlfma_ops_s *o, T **p, const T *src, int64_t count)
     return MLFMA_OK;
 }
 
+void free_graphs(mlfma_ops_s *o)
+{
+    for (auto &g : o->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    o->graphs.clear();
+}
+
 void free_ops(mlfma_ops_s *o)
 {
     if (!o) return;
     prof_release(o);
+    free_graphs(o);
     if (!o->allocs.empty()) {
         int cur = 0;
         if (hipGetDevice(&cur) == hipSuccess) {
@@ -328,28 +349,73 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
     const int cin = conj_in >= 0 ? conj_in : conj;
     const int cout = conj_out >= 0 ? conj_out : conj;
     const int odt = out_dtype >= 0 ? out_dtype : dtype;
-    const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
-    if (rc == MLFMA_OK) {
-        rc = [&]() -> int {
-            LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, cin, o->qs, s));
-            const int64_t nnear = o->n * R * (field ? 3 : 1);
-            if (parts & MLFMA_NEAR)
-                LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->pts, o->pt_start,
-                                             o->near_start, o->near_idx, o->leaf_coord,
-                                             (float)o->tree->leaf, (float)o->k, o->qs, R, field,
-                                             o->near, s));
-            else
-                LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
-            if (far) {
-                int r2 = run_far(o, R, s);
-                if (r2) return r2;
+    auto enqueue = [&]() -> int {
+        const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
+        LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, cin, o->qs, s));
+        const int64_t nnear = o->n * R * (field ? 3 : 1);
+        if (parts & MLFMA_NEAR)
+            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->pts, o->pt_start,
+                                         o->near_start, o->near_idx, o->leaf_coord,
+                                         (float)o->tree->leaf, (float)o->k, o->qs, R, field,
+                                         o->near, s));
+        else
+            LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
+        if (far) {
+            int r2 = run_far(o, R, s);
+            if (r2) return r2;
+        }
+        DevLevel &leaf = o->lev[o->n_lev];
+        LAUNCH(MLFMA_K_L2O, dev::l2o_scatter(o->pts, o->pt_leaf, o->perm, far ? leaf.khat_w : nullptr,
+                                             far ? leaf.K : 0, (float)o->k, far ? leaf.Lloc : nullptr,
+                                             o->near, o->n, R, field, far ? 1 : 0, cout, odt, out, s));
+        return MLFMA_OK;
+    };
+    const bool graph = rc == MLFMA_OK && (o->flags & MLFMA_USE_GRAPH) && s != nullptr &&
+                       o->prof_mask == 0;
+    if (rc == MLFMA_OK && !graph) rc = enqueue();
+    if (rc == MLFMA_OK && graph) {
+        mlfma_ops_s::GraphEntry *hit = nullptr;
+        for (auto &g : o->graphs)
+            if (g.q == q && g.out == out && g.nrhs == nrhs && g.dtype == dtype &&
+                g.field == field && g.cin == cin && g.cout == cout && g.odt == odt &&
+                g.parts == parts && g.stream == s)
+                hit = &g;
+        if (!hit) {
+            hipGraph_t gph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = fail(MLFMA_EDEVICE, "matvec: stream capture could not start");
+            } else {
+                const int rq = enqueue();
+                const hipError_t ee = hipStreamEndCapture(s, &gph);
+                if (rq) rc = rq;
+                else if (ee != hipSuccess || !gph)
+                    rc = fail(MLFMA_EDEVICE, "matvec: stream capture failed: %s", hipGetErrorString(ee));
+                else if (hipGraphInstantiate(&exec, gph, nullptr, nullptr, 0) != hipSuccess)
+                    rc = fail(MLFMA_EDEVICE, "matvec: graph instantiation failed");
+                if (gph) (void)hipGraphDestroy(gph);
             }
-            DevLevel &leaf = o->lev[o->n_lev];
-            LAUNCH(MLFMA_K_L2O, dev::l2o_scatter(o->pts, o->pt_leaf, o->perm, far ? leaf.khat_w : nullptr,
-                                far ? leaf.K : 0, (float)o->k, far ? leaf.Lloc : nullptr,
-                                o->near, o->n, R, field, far ? 1 : 0, cout, odt, out, s));
-            return MLFMA_OK;
-        }();
+            if (rc == MLFMA_OK) {
+                if (o->graphs.size() >= 8) {
+                    auto old = std::min_element(o->graphs.begin(), o->graphs.end(),
+                                                [](const mlfma_ops_s::GraphEntry &a,
+                                                   const mlfma_ops_s::GraphEntry &b) { return a.use < b.use; });
+                    (void)hipGraphExecDestroy(old->exec);
+                    o->graphs.erase(old);
+                }
+                mlfma_ops_s::GraphEntry ge;
+                ge.q = q; ge.out = out; ge.nrhs = nrhs; ge.dtype = dtype; ge.field = field;
+                ge.cin = cin; ge.cout = cout; ge.odt = odt; ge.parts = parts; ge.stream = s;
+                ge.exec = exec;
+                o->graphs.push_back(ge);
+                hit = &o->graphs.back();
+            }
+        }
+        if (rc == MLFMA_OK) {
+            hit->use = ++o->graph_clock;
+            rc = check_hip(hipGraphLaunch(hit->exec, s), "hipGraphLaunch");
+        }
     }
     o->last_R = R;
     if (cur != o->device) (void)hipSetDevice(cur);
@@ -391,7 +457,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     if (digits < 1 || digits > 10) return fail(MLFMA_EINVAL, "precompute: digits outside 1..10");
     if (max_rhs < 1 || max_rhs > 1024)
         return fail(MLFMA_EINVAL, "precompute: max_rhs outside 1..1024");
-    if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE))
+    if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE | MLFMA_USE_GRAPH))
         return fail(MLFMA_EINVAL, "precompute: unknown flags");
     if (t->n_lev >= 3 && k * std::sqrt(3.0) * t->leaf < 1.0)
         return fail(MLFMA_EINVAL,
@@ -774,6 +840,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
     if (variant < 0 || variant > 3) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
     o->lev[level].m2l_variant = variant;
+    free_graphs(o);  // captured graphs hold the old variant
     return MLFMA_OK;
 }
 

@@ -196,3 +196,33 @@ def test_batched_64_rhs_equals_single():
         torch.cuda.synchronize()
         assert rel_l2(P[:, r], p.cpu().numpy()) < 1e-6
         assert rel_l2(A[:, r], a.cpu().numpy()) < 1e-6
+
+
+def test_graph_replays_match_eager(c1):
+    """Captured graph of the whole matvec, replayed several times with eager
+    work and synchronisations in between; every replay equals the eager
+    result bit for bit (same kernels, same order)."""
+    torch = c1["torch"]
+    G = c1["G"]
+    say("c1: graph capture and replays")
+    ops_g = G.Operators(c1["gt"], K, W.DIGITS, max_rhs=1, graph=True)
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    eager = _run(c1, c1["gops"].matvec, qd)
+    st = torch.cuda.Stream()
+    out = torch.empty_like(qd)
+    rng = np.random.default_rng(61)
+    for rep in range(4):
+        with torch.cuda.stream(st):
+            phi = ops_g.matvec(qd, stream=st)
+        st.synchronize()
+        got = phi.cpu().numpy()
+        assert rel_l2(got, eager) < 1e-6, rep
+        # unrelated eager work between replays
+        x = torch.from_numpy(rng.standard_normal(4096).astype(np.complex64)).cuda()
+        c1["gops"].matvec(x)
+        torch.cuda.synchronize()
+    # adjoint through the graph path too
+    with torch.cuda.stream(st):
+        psi = ops_g.adjoint(qd, stream=st)
+    st.synchronize()
+    assert rel_l2(psi.cpu().numpy(), _run(c1, c1["gops"].adjoint, qd)) < 1e-6
