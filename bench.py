@@ -34,15 +34,19 @@ PEAK_BF16_TFLOPS = 2500.0       # dense BF16 MFMA
 # bound of each kernel as implemented
 BOUND = {"gather": "hbm", "p2p": "alu", "c2m": "alu", "interp_s1": "mfma",
          "interp_s2": "mfma", "interp_s3": "mfma", "m2l": "alu", "anterp_s1": "mfma",
-         "anterp_s2": "mfma", "anterp_s3": "mfma", "l2o": "alu"}
+         "anterp_s2": "mfma", "anterp_s3": "mfma", "l2o": "alu", "interp": "mfma",
+         "anterp": "mfma"}
 
 
-def algorithmic_work(tinfo, levels, R):
+def algorithmic_work(tinfo, levels, R, onepass_up=None, onepass_down=None):
     """Algorithmic bytes and flops of each kernel for one step with R
     right-hand sides (complex64 = 8 bytes; a complex multiply-add = 8 flops;
     a complex-by-real multiply-add = 4 flops; sin, cos and rsqrt count as one
     flop each).  Each quantity is the minimum the method must move or
-    compute, not what a kernel happens to do."""
+    compute, not what a kernel happens to do.  onepass_up / onepass_down
+    list, per level, whether the pair (l, l+1) runs the one-pass kernel
+    (its work is then booked on "interp" / "anterp", else on the three
+    staged kernels)."""
     N = tinfo["n_points"]
     nl = tinfo["n_levels"]
     lv = {d["level"]: d for d in levels}
@@ -68,18 +72,34 @@ def algorithmic_work(tinfo, levels, R):
             p, c = lv[l], lv[l + 1]
             M = 2 * c["L"] + 1
             Bc, Bp = c["nbox"] * R, p["nbox"] * R
-            w["interp_s1"]["flops"] += 4.0 * Bc * c["ntheta"] * c["nphi"] * M
-            w["interp_s1"]["bytes"] += 8.0 * Bc * (c["K"] + c["ntheta"] * M)
-            w["interp_s2"]["flops"] += 4.0 * Bc * M * p["ntheta"] * c["ntheta"]
-            w["interp_s2"]["bytes"] += 8.0 * Bc * M * (c["ntheta"] + p["ntheta"])
-            w["interp_s3"]["flops"] += 4.0 * Bc * p["ntheta"] * M * p["nphi"] + 8.0 * Bc * p["K"]
-            w["interp_s3"]["bytes"] += 8.0 * (Bc * p["ntheta"] * M + Bp * p["K"])
-            w["anterp_s1"]["flops"] += 4.0 * Bc * p["ntheta"] * p["nphi"] * M + 8.0 * Bc * p["K"]
-            w["anterp_s1"]["bytes"] += 8.0 * (Bc * p["ntheta"] * M + Bp * p["K"])
-            w["anterp_s2"]["flops"] += 4.0 * Bc * M * c["ntheta"] * p["ntheta"]
-            w["anterp_s2"]["bytes"] += 8.0 * Bc * M * (c["ntheta"] + p["ntheta"])
-            w["anterp_s3"]["flops"] += 4.0 * Bc * c["ntheta"] * M * c["nphi"]
-            w["anterp_s3"]["bytes"] += 8.0 * Bc * (c["ntheta"] * M + 2 * c["K"])
+            f1 = 4.0 * Bc * c["ntheta"] * c["nphi"] * M
+            f2 = 4.0 * Bc * M * p["ntheta"] * c["ntheta"]
+            f3 = 4.0 * Bc * p["ntheta"] * M * p["nphi"] + 8.0 * Bc * p["K"]
+            g1 = 4.0 * Bc * p["ntheta"] * p["nphi"] * M + 8.0 * Bc * p["K"]
+            g2 = 4.0 * Bc * M * c["ntheta"] * p["ntheta"]
+            g3 = 4.0 * Bc * c["ntheta"] * M * c["nphi"]
+            up = bool(onepass_up and onepass_up[l - 1] == 1)
+            dn = bool(onepass_down and onepass_down[l - 1] == 1)
+            if up:
+                w["interp"]["flops"] += f1 + f2 + f3
+                w["interp"]["bytes"] += 8.0 * (Bc * c["K"] + Bp * p["K"])
+            if dn:
+                w["anterp"]["flops"] += g1 + g2 + g3
+                w["anterp"]["bytes"] += 8.0 * (Bp * p["K"] + 2 * Bc * c["K"])
+            if not up:
+                w["interp_s1"]["flops"] += f1
+                w["interp_s1"]["bytes"] += 8.0 * Bc * (c["K"] + c["ntheta"] * M)
+                w["interp_s2"]["flops"] += f2
+                w["interp_s2"]["bytes"] += 8.0 * Bc * M * (c["ntheta"] + p["ntheta"])
+                w["interp_s3"]["flops"] += f3
+                w["interp_s3"]["bytes"] += 8.0 * (Bc * p["ntheta"] * M + Bp * p["K"])
+            if not dn:
+                w["anterp_s1"]["flops"] += g1
+                w["anterp_s1"]["bytes"] += 8.0 * (Bc * p["ntheta"] * M + Bp * p["K"])
+                w["anterp_s2"]["flops"] += g2
+                w["anterp_s2"]["bytes"] += 8.0 * Bc * M * (c["ntheta"] + p["ntheta"])
+                w["anterp_s3"]["flops"] += g3
+                w["anterp_s3"]["bytes"] += 8.0 * Bc * (c["ntheta"] * M + 2 * c["K"])
     return w
 
 
@@ -219,7 +239,7 @@ def main():
         torch.cuda.synchronize()
         adj_ms = (time.perf_counter() - ta) * 1e3 / args.steps
 
-    work = algorithmic_work(tinfo, levels, R)
+    work = algorithmic_work(tinfo, levels, R, ops.variants("interp"), ops.variants("anterp"))
     rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
     value = xyz.shape[0] * R / (ms_per_step * 1e-3)
     out = {
@@ -239,6 +259,8 @@ def main():
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
         "m2l_variant_per_level": ops.variants("m2l"),
+        "onepass_interp_per_level": ops.variants("interp"),
+        "onepass_anterp_per_level": ops.variants("anterp"),
         "roofline": rl,
     }
     if not args.no_cpu_baseline:

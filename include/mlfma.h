@@ -266,7 +266,9 @@ enum mlfma_kernel_id {
     MLFMA_K_ANTERP_S2 = 8, /* L2L: per-order theta maps                      */
     MLFMA_K_ANTERP_S3 = 9, /* L2L: phi synthesis + add                       */
     MLFMA_K_L2O = 10,      /* leaf evaluation + near + scatter               */
-    MLFMA_K_COUNT = 11
+    MLFMA_K_INTERP = 11,   /* M2M in one pass (the three maps in LDS)        */
+    MLFMA_K_ANTERP = 12,   /* L2L in one pass                                */
+    MLFMA_K_COUNT = 13
 };
 
 /*
@@ -286,10 +288,15 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * (out[l-1] for levels 1..n_levels; -1 where a level has no such kernel).
  * kernel = MLFMA_K_M2L: 0 per-observer lists from L2, 1 operators staged in
  * LDS, 2 sibling groups, 3 sibling groups with per-source records.
+ * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
+ * and l+1, -1 on the leaf level and above level 3): 0 three passes through
+ * HBM (ids _S1.._S3), 1 one pass with the intermediates in LDS.
  */
 int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
-/* Diagnostics: force a variant of `kernel` on `level` (3..n_levels); used by
- * the tests to check every variant.  EINVAL for an unknown variant. */
+/* Diagnostics: force a variant of `kernel` on `level` (3..n_levels; for the
+ * interpolation ids 3..n_levels-1); used by the tests to check every
+ * variant.  EINVAL for an unknown variant, or for the one-pass variant where
+ * its LDS plan does not fit or MLFMA_BF16X3_INTERP is set. */
 int mlfma_ops_set_variant(mlfma_ops_t ops, int kernel, int level, int variant);
 
 /*

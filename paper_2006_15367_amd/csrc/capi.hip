@@ -45,9 +45,12 @@ struct DevLevel {
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     float2 *S = nullptr, *Lloc = nullptr;  // [nbox][R][K]
     int Lc = 0, Mc = 0;
-    float2 *shift = nullptr;
+    float2 *shift = nullptr, *shift_axis = nullptr;
     float *iF = nullptr, *iA = nullptr, *iG = nullptr;
     float *aF = nullptr, *aB = nullptr, *aG = nullptr;
+    // level pair (this level = parent): 0 three passes through HBM, 1 one pass
+    int interp_variant = 0, anterp_variant = 0;
+    bool onepass_ok = false;         // the one-pass kernels fit in LDS
 };
 
 }  // namespace
@@ -247,10 +250,70 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s)
     }
 }
 
-// Autotuner: per level, time every M2L variant (HIP events, 3 runs each,
-// best of 3) at the handle's max_rhs and keep the fastest.  The results of
-// the variants are identical up to summation order.
-int autotune_m2l(mlfma_ops_s *o)
+// One-pass interpolation / anterpolation of the level pair (l, l+1).
+hipError_t launch_interp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s)
+{
+    DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+    return dev::interp_fused(P.nbox, R, C.L, P.L, P.child_start, C.oct, C.S, P.iF, P.iA, P.iG,
+                             P.shift_axis, P.S, s);
+}
+
+hipError_t launch_anterp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s)
+{
+    DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+    return dev::anterp_fused(P.nbox, R, C.L, P.L, P.child_start, C.oct, P.Lloc, P.aF, P.aB, P.aG,
+                             P.shift_axis, C.Lloc, s);
+}
+
+// Three-pass interpolation / anterpolation of the level pair (l, l+1).
+hipError_t launch_interp_staged(mlfma_ops_s *o, int l, int R, hipStream_t s)
+{
+    DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+    const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
+    hipError_t e = dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, P.Mc, o->X1, s, b3);
+    if (e == hipSuccess)
+        e = dev::theta_map(o->X1, C.nbox * R, C.nth, P.Mc, P.iA, P.nth, o->X2, s, b3);
+    if (e == hipSuccess)
+        e = dev::interp_s3(P.nbox, R, P.nth, P.nph, P.Mc, P.child_start, C.oct, o->X2, P.iG,
+                           P.shift, P.S, s);
+    return e;
+}
+
+hipError_t launch_anterp_staged(mlfma_ops_s *o, int l, int R, hipStream_t s)
+{
+    DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+    const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
+    hipError_t e = dev::anterp_s1(P.Lloc, C.parent, C.oct, C.nbox, R, P.nth, P.nph, P.shift,
+                                  P.aF, P.Mc, o->X1, s, b3);
+    if (e == hipSuccess)
+        e = dev::theta_map(o->X1, C.nbox * R, P.nth, P.Mc, P.aB, C.nth, o->X2, s, b3);
+    if (e == hipSuccess)
+        e = dev::anterp_s3(C.nbox, R, C.nth, C.nph, P.Mc, o->X2, P.aG, C.Lloc, s, b3);
+    return e;
+}
+
+// Best of 3 HIP-event timings of one launch sequence; negative on failure.
+template <class F>
+float time_best(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F &&run)
+{
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(e0, s);
+        const hipError_t e = run();
+        (void)hipEventRecord(e1, s);
+        if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        tmin = std::min(tmin, ms);
+    }
+    return tmin;
+}
+
+// Autotuner: per level, time every M2L variant and, per level pair, the
+// one-pass and three-pass interpolation and anterpolation (HIP events,
+// best of 3) at the handle's max_rhs, and keep the fastest.  The variants
+// compute the same result up to summation order.
+int autotune(mlfma_ops_s *o)
 {
     if (o->n_lev < 3) return MLFMA_OK;
     hipStream_t s;
@@ -258,32 +321,38 @@ int autotune_m2l(mlfma_ops_s *o)
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
+    const int R = o->max_rhs;
     int rc = MLFMA_OK;
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
         for (int v = 0; v < 4; ++v) {
-            float tmin = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                (void)hipEventRecord(e0, s);
-                hipError_t e = launch_m2l(o, l, v, o->max_rhs, s);
-                (void)hipEventRecord(e1, s);
-                if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed: %s", v,
-                              hipGetErrorString(e));
-                    break;
-                }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                tmin = std::min(tmin, ms);
+            const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
+            if (t < 0.f) {
+                rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
+                break;
             }
-            if (rc) break;
-            if (tmin < best) {
-                best = tmin;
+            if (t < best) {
+                best = t;
                 bestv = v;
             }
         }
         o->lev[l].m2l_variant = bestv;
+    }
+    const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
+    for (int l = 3; l < o->n_lev && rc == MLFMA_OK; ++l) {
+        DevLevel &P = o->lev[l];
+        if (!P.onepass_ok || b3) continue;
+        const float ts = time_best(s, e0, e1, [&] { return launch_interp_staged(o, l, R, s); });
+        const float tf = time_best(s, e0, e1, [&] { return launch_interp_onepass(o, l, R, s); });
+        const float as = time_best(s, e0, e1, [&] { return launch_anterp_staged(o, l, R, s); });
+        const float af = time_best(s, e0, e1, [&] { return launch_anterp_onepass(o, l, R, s); });
+        if (ts < 0.f || tf < 0.f || as < 0.f || af < 0.f) {
+            rc = fail(MLFMA_EDEVICE, "autotune: interpolation variants failed on level %d", l);
+            break;
+        }
+        P.interp_variant = tf < ts ? 1 : 0;
+        P.anterp_variant = af < as ? 1 : 0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -303,6 +372,10 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s)
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
+        if (P.interp_variant == 1) {
+            LAUNCH(MLFMA_K_INTERP, launch_interp_onepass(o, l, R, s));
+            continue;
+        }
         LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s, b3));
         LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s, b3));
         LAUNCH(MLFMA_K_INTERP_S3, dev::interp_s3(P.nbox, R, P.nth, P.nph, M, P.child_start, C.oct, o->X2, P.iG,
@@ -315,6 +388,10 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s)
     for (int l = 3; l < nl; ++l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
+        if (P.anterp_variant == 1) {
+            LAUNCH(MLFMA_K_ANTERP, launch_anterp_onepass(o, l, R, s));
+            continue;
+        }
         LAUNCH(MLFMA_K_ANTERP_S1, dev::anterp_s1(P.Lloc, C.parent, C.oct, C.nbox, R, P.nth, P.nph, P.shift, P.aF, M,
                           o->X1, s, b3));
         LAUNCH(MLFMA_K_ANTERP_S2, dev::theta_map(o->X1, C.nbox * R, P.nth, M, P.aB, C.nth, o->X2, s, b3));
@@ -511,6 +588,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             if (l < nl) {
                 const LevelTables &C = o->tab[l + 1];
                 pl.add(8 * T.K * 8);
+                pl.add((int64_t)T.shift_axis.size() * 4);
                 pl.add(((int64_t)T.iF.size() + T.iA.size() + T.iG.size() + T.aF.size() +
                         T.aB.size() + T.aG.size()) * 4);
                 const int64_t e = t->lev[l + 1].nbox * R * std::max(C.nth, T.nth) * T.Mc;
@@ -645,6 +723,9 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 D.Lc = T.Lc;
                 D.Mc = T.Mc;
                 if ((r = upload(o, &D.shift, (const float2 *)T.shift.data(), 8 * T.K))) return r;
+                if ((r = upload(o, &D.shift_axis, (const float2 *)T.shift_axis.data(),
+                                (int64_t)T.shift_axis.size() / 2)))
+                    return r;
                 if ((r = upload(o, &D.iF, T.iF.data(), (int64_t)T.iF.size()))) return r;
                 if ((r = upload(o, &D.iA, T.iA.data(), (int64_t)T.iA.size()))) return r;
                 if ((r = upload(o, &D.iG, T.iG.data(), (int64_t)T.iG.size()))) return r;
@@ -656,14 +737,23 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         o->scratch_elems = scratch;
         if ((r = dalloc(o, &o->X1, scratch))) return r;
         if ((r = dalloc(o, &o->X2, scratch))) return r;
-        // spectra start zeroed (the autotuner runs M2L on them)
+        // spectra start zeroed (the autotuner runs the kernels on them)
         for (int l = 3; l <= nl; ++l) {
             DevLevel &D = o->lev[l];
-            if (hipMemset(D.S, 0, (size_t)(D.nbox * R * D.K) * sizeof(float2)) != hipSuccess)
+            if (hipMemset(D.S, 0, (size_t)(D.nbox * R * D.K) * sizeof(float2)) != hipSuccess ||
+                hipMemset(D.Lloc, 0, (size_t)(D.nbox * R * D.K) * sizeof(float2)) != hipSuccess)
                 return fail(MLFMA_EDEVICE, "hipMemset failed");
         }
+        // one-pass interpolation where its LDS plan fits; FP32 path only
+        for (int l = 3; l < nl; ++l) {
+            DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+            P.onepass_ok = dev::pair_onepass_fits(C.L, P.L);
+            const bool use = P.onepass_ok && !(flags & MLFMA_BF16X3_INTERP);
+            P.interp_variant = use ? 1 : 0;
+            P.anterp_variant = use ? 1 : 0;
+        }
         if (!(flags & MLFMA_NO_AUTOTUNE)) {
-            if ((r = autotune_m2l(o))) return r;
+            if ((r = autotune(o))) return r;
         }
         return MLFMA_OK;
     }();
@@ -827,19 +917,41 @@ int mlfma_copy_spectra(mlfma_ops_t o, int level, int which, int64_t nrhs, void *
 int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
 {
     if (!o || !out) return fail(MLFMA_EINVAL, "ops_variants: null argument");
-    if (kernel != MLFMA_K_M2L) return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
-    for (int l = 1; l <= o->n_lev && l <= max_entries; ++l)
-        out[l - 1] = l >= 3 ? o->lev[l].m2l_variant : -1;
-    return MLFMA_OK;
+    if (kernel == MLFMA_K_M2L) {
+        for (int l = 1; l <= o->n_lev && l <= max_entries; ++l)
+            out[l - 1] = l >= 3 ? o->lev[l].m2l_variant : -1;
+        return MLFMA_OK;
+    }
+    if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
+        for (int l = 1; l <= o->n_lev && l <= max_entries; ++l)
+            out[l - 1] = (l >= 3 && l < o->n_lev)
+                             ? (kernel == MLFMA_K_INTERP ? o->lev[l].interp_variant
+                                                         : o->lev[l].anterp_variant)
+                             : -1;
+        return MLFMA_OK;
+    }
+    return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
 }
 
 int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
 {
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
-    if (kernel != MLFMA_K_M2L) return fail(MLFMA_EINVAL, "ops_set_variant: kernel %d has no variants", kernel);
-    if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-    if (variant < 0 || variant > 3) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
-    o->lev[level].m2l_variant = variant;
+    if (kernel == MLFMA_K_M2L) {
+        if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
+        if (variant < 0 || variant > 3) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        o->lev[level].m2l_variant = variant;
+    } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
+        if (level < 3 || level >= o->n_lev)
+            return fail(MLFMA_EINVAL, "ops_set_variant: bad level pair %d", level);
+        if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant == 1 && (!o->lev[level].onepass_ok || (o->flags & MLFMA_BF16X3_INTERP)))
+            return fail(MLFMA_EINVAL, "ops_set_variant: one-pass kernel unavailable on level pair %d",
+                        level);
+        (kernel == MLFMA_K_INTERP ? o->lev[level].interp_variant : o->lev[level].anterp_variant) =
+            variant;
+    } else {
+        return fail(MLFMA_EINVAL, "ops_set_variant: kernel %d has no variants", kernel);
+    }
     free_graphs(o);  // captured graphs hold the old variant
     return MLFMA_OK;
 }

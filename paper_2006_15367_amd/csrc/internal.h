@@ -69,6 +69,8 @@ struct LevelTables {
     // level pair (this level = parent p, level+1 = child c); empty at the leaf
     int Lc = 0, Mc = 0;              // child order, 2 Lc + 1 real-DFT columns
     std::vector<float> shift;        // [8][K][2] exp(-i k khat.(c_c - c_p))
+    std::vector<float> shift_axis;   // [2K + nth][2]: exp(-i k (a/4) khat_x) over the grid,
+                                     // the same for khat_y, then for khat_z per theta node
     std::vector<float> iF;           // [nph_c][Mc]   child-grid real DFT
     std::vector<float> iA;           // [Lc+1][nth_c][nth] theta maps (input index first)
     std::vector<float> iG;           // [Mc][nph]     parent-grid synthesis

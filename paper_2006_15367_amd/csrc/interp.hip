@@ -48,6 +48,11 @@ struct ProbS1 {
     int64_t nrows, BR;
     int K, N, nth;
     __device__ float2 a(int64_t row, int k) const { return X[row * K + k]; }
+    struct Row {
+        const float2 *x;
+    };
+    __device__ Row row_at(int64_t row) const { return Row{X + row * K}; }
+    __device__ float2 at(const Row &w, int k) const { return w.x[k]; }
     __device__ float b(int k, int n) const { return F[k * N + n]; }
     __device__ void store(int64_t row, int n, float2 v) const
     {
@@ -78,6 +83,25 @@ struct ProbS1L {
         const float2 s = shift[(int64_t)oct[c] * Kp + th * K + k];
         return make_float2(s.x * x.x + s.y * x.y, s.x * x.y - s.y * x.x);
     }
+    // row (c, r, theta) decoded once; then K contiguous samples of the
+    // parent's local and of the shift
+    struct Row {
+        const float2 *x, *s;
+    };
+    __device__ Row row_at(int64_t row) const
+    {
+        const int cr = (int)row / nth;
+        const int th = (int)row - cr * nth;
+        const int c = cr / R;
+        const int r = cr - c * R;
+        return Row{Lp + ((int64_t)parent[c] * R + r) * Kp + th * K,
+                   shift + (int64_t)oct[c] * Kp + th * K};
+    }
+    __device__ float2 at(const Row &w, int k) const
+    {
+        const float2 x = w.x[k], s = w.s[k];
+        return make_float2(s.x * x.x + s.y * x.y, s.x * x.y - s.y * x.x);
+    }
     __device__ float b(int k, int n) const { return F[k * N + n]; }
     __device__ void store(int64_t row, int n, float2 v) const
     {
@@ -100,6 +124,11 @@ struct ProbS2 {
     {
         return T1[((int64_t)col * nrows + row) * K + k];
     }
+    struct Row {
+        const float2 *x;
+    };
+    __device__ Row row_at(int64_t row) const { return Row{T1 + ((int64_t)col * nrows + row) * K}; }
+    __device__ float2 at(const Row &w, int k) const { return w.x[k]; }
     __device__ float b(int k, int n) const
     {
         const int m = (col + 1) >> 1;
@@ -129,6 +158,11 @@ struct ProbS3L {
         const int th = (int)row - cr * nth;
         return T2[((int64_t)cr * K + k) * nth + th];
     }
+    struct Row {
+        int64_t row;
+    };
+    __device__ Row row_at(int64_t row) const { return Row{row}; }
+    __device__ float2 at(const Row &w, int k) const { return a(w.row, k); }
     __device__ float b(int k, int n) const { return G[k * N + n]; }
     __device__ void store(int64_t row, int n, float2 v) const
     {
@@ -293,28 +327,32 @@ __global__ void __launch_bounds__(256) k_rowgemm_lds(P p, int col_override)
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int64_t rbase = tile * 32;
             __syncthreads();
-            for (int base = threadIdx.x; base < 32 * K4; base += 4 * blockDim.x) {
-                float2 v[4];
-                int dst[4];
+            if (P::rows_fast) {
+                for (int base = threadIdx.x; base < 32 * K4; base += 4 * blockDim.x) {
+                    float2 v[4];
+                    int dst[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int idx = base + u * blockDim.x;
-                    int rl, k;
-                    if (P::rows_fast) {
-                        k = idx >> 5;
-                        rl = idx & 31;
-                    } else {
-                        rl = idx / K4;
-                        k = idx - rl * K4;
+                    for (int u = 0; u < 4; ++u) {
+                        const int idx = base + u * blockDim.x;
+                        const int k = idx >> 5, rl = idx & 31;
+                        const int64_t row = rbase + rl;
+                        dst[u] = idx < 32 * K4 ? rl * KP + k : -1;
+                        v[u] = (dst[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
+                                                                        : make_float2(0.f, 0.f);
                     }
-                    const int64_t row = rbase + rl;
-                    dst[u] = idx < 32 * K4 ? rl * KP + k : -1;
-                    v[u] = (dst[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
-                                                                    : make_float2(0.f, 0.f);
-                }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (dst[u] >= 0) As[dst[u]] = v[u];
+                    for (int u = 0; u < 4; ++u)
+                        if (dst[u] >= 0) As[dst[u]] = v[u];
+                }
+            } else {
+                // 8 threads per row: the row is decoded once, its K samples
+                // are contiguous
+                const int rl = threadIdx.x >> 3;
+                const int64_t row = rbase + rl;
+                const bool ok = row < p.nrows;
+                const typename P::Row w = p.row_at(ok ? row : 0);
+                for (int k = threadIdx.x & 7; k < K4; k += 8)
+                    As[rl * KP + k] = (ok && k < K) ? p.at(w, k) : make_float2(0.f, 0.f);
             }
             __syncthreads();
             const int64_t row0 = rbase + wave * 8;
@@ -413,36 +451,47 @@ __global__ void __launch_bounds__(256) k_rowgemm_bf16x3(P p, int col_override)
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int64_t rbase = tile * 32;
             __syncthreads();
-            for (int base = threadIdx.x; base < 32 * K32; base += 4 * blockDim.x) {
-                float2 v[4];
-                int rl_[4], k_[4];
+            if (P::rows_fast) {
+                for (int base = threadIdx.x; base < 32 * K32; base += 4 * blockDim.x) {
+                    float2 v[4];
+                    int rl_[4], k_[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int idx = base + u * blockDim.x;
-                    int rl, k;
-                    if (P::rows_fast) {
-                        k = idx >> 5;
-                        rl = idx & 31;
-                    } else {
-                        rl = idx / K32;
-                        k = idx - rl * K32;
+                    for (int u = 0; u < 4; ++u) {
+                        const int idx = base + u * blockDim.x;
+                        const int k = idx >> 5, rl = idx & 31;
+                        rl_[u] = idx < 32 * K32 ? rl : -1;
+                        k_[u] = k;
+                        const int64_t row = rbase + rl;
+                        v[u] = (rl_[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
+                                                                        : make_float2(0.f, 0.f);
                     }
-                    rl_[u] = idx < 32 * K32 ? rl : -1;
-                    k_[u] = k;
-                    const int64_t row = rbase + rl;
-                    v[u] = (rl_[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
-                                                                    : make_float2(0.f, 0.f);
-                }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (rl_[u] < 0) continue;
+                    for (int u = 0; u < 4; ++u) {
+                        if (rl_[u] < 0) continue;
+                        unsigned short h, l;
+                        split_bf16(v[u].x, h, l);
+                        Ah[(2 * rl_[u]) * KP + k_[u]] = h;
+                        Al[(2 * rl_[u]) * KP + k_[u]] = l;
+                        split_bf16(v[u].y, h, l);
+                        Ah[(2 * rl_[u] + 1) * KP + k_[u]] = h;
+                        Al[(2 * rl_[u] + 1) * KP + k_[u]] = l;
+                    }
+                }
+            } else {
+                // 8 threads per row, row decoded once
+                const int rl = threadIdx.x >> 3;
+                const int64_t row = rbase + rl;
+                const bool ok = row < p.nrows;
+                const typename P::Row w = p.row_at(ok ? row : 0);
+                for (int k = threadIdx.x & 7; k < K32; k += 8) {
+                    const float2 v = (ok && k < K) ? p.at(w, k) : make_float2(0.f, 0.f);
                     unsigned short h, l;
-                    split_bf16(v[u].x, h, l);
-                    Ah[(2 * rl_[u]) * KP + k_[u]] = h;
-                    Al[(2 * rl_[u]) * KP + k_[u]] = l;
-                    split_bf16(v[u].y, h, l);
-                    Ah[(2 * rl_[u] + 1) * KP + k_[u]] = h;
-                    Al[(2 * rl_[u] + 1) * KP + k_[u]] = l;
+                    split_bf16(v.x, h, l);
+                    Ah[(2 * rl) * KP + k] = h;
+                    Al[(2 * rl) * KP + k] = l;
+                    split_bf16(v.y, h, l);
+                    Ah[(2 * rl + 1) * KP + k] = h;
+                    Al[(2 * rl + 1) * KP + k] = l;
                 }
             }
             __syncthreads();

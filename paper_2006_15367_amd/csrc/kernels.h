@@ -56,6 +56,22 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M,
 hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
                      const float2 *Yh, const float *G, float2 *Lc, hipStream_t s, bool bf16x3);
 
+// One-pass M2M / L2L of a level pair (fused.hip): the three maps run back to
+// back in LDS per parent box and right-hand side.  Lc, Lp: bands of the
+// child and parent levels (only instantiated pairs, see pair_onepass_fits).
+// M2M: Sp[p][r] = sum_{c in p} shift[oct c] (.) interp(Sc[c][r])
+// L2L: Lch[c][r] += anterp(conj(shift[oct c]) (.) Lpar[parent c][r])
+// F [nphi_in][M], A [(M+1)/2][ntheta_in][ntheta_out], G [M][nphi_out];
+// E3: the axis factors of the shift on the parent grid.
+bool pair_onepass_fits(int Lc, int Lp);
+hipError_t interp_fused(int64_t nboxp, int R, int Lc, int Lp, const int32_t *child_start,
+                        const uint8_t *child_oct, const float2 *Sc, const float *F, const float *A,
+                        const float *G, const float2 *E3, float2 *Sp, hipStream_t s);
+hipError_t anterp_fused(int64_t nboxp, int R, int Lc, int Lp, const int32_t *child_start,
+                        const uint8_t *child_oct, const float2 *Lpar, const float *F,
+                        const float *B, const float *G, const float2 *E3, float2 *Lch,
+                        hipStream_t s);
+
 // out[i][a] = sum_r Re[conj(g[i][r]) Fq[i][r][a] + q[i][r] Fg[i][r][a]]
 // (q, g caller order, dtype 0 = complex64 / 1 = complex128; out float/double)
 hipError_t position_grad_combine(const void *q, const void *g, int dtype, const float2 *Fq,

@@ -265,6 +265,24 @@ int build_level_tables(const Tree &t, double k, int digits, std::vector<LevelTab
                     }
                 }
             }
+            // axis factors of the shift: the octant's shift is their product,
+            // each conjugated where the octant bit is 0
+            P.shift_axis.resize((size_t)2 * (2 * P.K + P.nth));
+            for (int i = 0; i < P.nth; ++i) {
+                const double st = std::sqrt((1.0 - P.x[i]) * (1.0 + P.x[i]));
+                for (int j = 0; j < P.nph; ++j) {
+                    const double ph = 2.0 * M_PI * j / P.nph;
+                    const size_t e = (size_t)i * P.nph + j;
+                    const double ax = k * q * st * std::cos(ph), ay = k * q * st * std::sin(ph);
+                    P.shift_axis[2 * e] = (float)std::cos(ax);
+                    P.shift_axis[2 * e + 1] = (float)(-std::sin(ax));
+                    P.shift_axis[2 * (P.K + e)] = (float)std::cos(ay);
+                    P.shift_axis[2 * (P.K + e) + 1] = (float)(-std::sin(ay));
+                }
+                const double az = k * q * P.x[i];
+                P.shift_axis[2 * (2 * P.K + i)] = (float)std::cos(az);
+                P.shift_axis[2 * (2 * P.K + i) + 1] = (float)(-std::sin(az));
+            }
             real_dft(C.nph, P.Mc, P.iF);
             legendre_maps(C.L, C.x, C.wx, P.x, P.iA);
             real_synthesis(P.Mc, P.nph, P.iG);

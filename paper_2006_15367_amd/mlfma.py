@@ -18,7 +18,7 @@ C64, C128 = 0, 1
 NEAR, FAR, CONJ = 1, 2, 4
 FP32, BF16X3_INTERP, NO_AUTOTUNE, USE_GRAPH = 0, 1, 2, 4
 KERNELS = ["gather", "p2p", "c2m", "interp_s1", "interp_s2", "interp_s3", "m2l",
-           "anterp_s1", "anterp_s2", "anterp_s3", "l2o"]
+           "anterp_s1", "anterp_s2", "anterp_s3", "l2o", "interp", "anterp"]
 
 _lib = None
 

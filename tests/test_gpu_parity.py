@@ -159,6 +159,37 @@ def test_every_m2l_variant(c1, variant):
     assert rel_l2(phi, c1["ophi"]) < 1e-4
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_interpolation_variants(c1, variant):
+    """Three-pass (0) and one-pass (1) M2M / L2L: per-level multipoles and
+    locals against the oracle, then end to end."""
+    torch = c1["torch"]
+    say("c1: interpolation variant", variant)
+    qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
+    ops = c1["gops"]
+    nl = c1["ot"].n_lev
+    chosen = {k: ops.variants(k) for k in ("interp", "anterp")}
+    try:
+        for k in ("interp", "anterp"):
+            for l in range(3, nl):
+                ops.set_variant(l, variant, kernel=k)
+        assert ops.variants("interp")[2:nl - 1] == [variant] * (nl - 3)
+        phi = _run(c1, ops.matvec, qd)
+        for l in range(3, nl + 1):
+            S = ops.copy_spectra(l, 0).cpu().numpy()
+            Lg = ops.copy_spectra(l, 1).cpu().numpy()
+            torch.cuda.synchronize()
+            e_s, e_l = rel_l2(S, c1["inter"]["S"][l]), rel_l2(Lg, c1["inter"]["L"][l])
+            say("variant", variant, "level", l, "S err", e_s, "L err", e_l)
+            assert e_s < 1e-5
+            assert e_l < 1e-4
+    finally:
+        for k in ("interp", "anterp"):
+            for l in range(3, nl):
+                ops.set_variant(l, chosen[k][l - 1], kernel=k)
+    assert rel_l2(phi, c1["ophi"]) < 1e-4
+
+
 def test_bf16x3_interpolation_accuracy(c1):
     """BF16 split-precision interpolation: same accuracy class as FP32."""
     torch = c1["torch"]
