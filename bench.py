@@ -103,6 +103,37 @@ def algorithmic_work(tinfo, levels, R, onepass_up=None, onepass_down=None):
     return w
 
 
+# source file of each kernel: a recorded traffic measurement is used only
+# while this file is unchanged
+KERNEL_SOURCE = {"m2l": "m2l.hip", "interp": "fused.hip", "anterp": "fused.hip",
+                 "p2p": "kernels.hip", "c2m": "kernels.hip", "l2o": "kernels.hip",
+                 "gather": "kernels.hip"}
+for _k in ("interp_s1", "interp_s2", "interp_s3", "anterp_s1", "anterp_s2", "anterp_s3"):
+    KERNEL_SOURCE[_k] = "interp.hip"
+
+
+def recorded_traffic(kernel, workload, nrhs):
+    """HBM bytes per launch of `kernel` on `workload`, from the committed
+    rocprofv3 counter summary profiles/<kernel>_<workload>_hbm_traffic.txt
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by the copy-kernel factors), or
+    None when there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.txt" % (kernel, workload))
+    src = KERNEL_SOURCE.get(kernel)
+    if not src or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    with open(os.path.join(ROOT, "paper_2006_15367_amd", "csrc", src), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("source_sha256") != digest or int(kv.get("nrhs", -1)) != nrhs:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def roofline(kernel, work, ms_per_step, launches_per_step, bf16x3):
     bound = BOUND[kernel]
     sec = ms_per_step * 1e-3
@@ -241,6 +272,9 @@ def main():
 
     work = algorithmic_work(tinfo, levels, R, ops.variants("interp"), ops.variants("anterp"))
     rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
+    rl["traffic"] = recorded_traffic(dominant, args.workload, R)
+    if rl["traffic"] is not None:
+        rl["algorithmic_bytes_per_launch"] = round(work[dominant]["bytes"] / max(1, launches), 1)
     value = xyz.shape[0] * R / (ms_per_step * 1e-3)
     out = {
         "metric": "MLFMA matvec points/s at 1e-3 rel-L2 (+adjoint)",
