@@ -442,6 +442,13 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
             if (r2) return r2;
         }
         DevLevel &leaf = o->lev[o->n_lev];
+        if (far && !field && R >= 8) {
+            // many right-hand sides: per-leaf product on the matrix cores
+            LAUNCH(MLFMA_K_L2O, dev::l2o_leaf_mfma(o->pts, o->pt_start, leaf.nbox, o->perm,
+                                                   leaf.khat_w, leaf.K, (float)o->k, leaf.Lloc,
+                                                   o->near, R, cout, odt, out, s));
+            return MLFMA_OK;
+        }
         LAUNCH(MLFMA_K_L2O, dev::l2o_scatter(o->pts, o->pt_leaf, o->perm, far ? leaf.khat_w : nullptr,
                                              far ? leaf.K : 0, (float)o->k, far ? leaf.Lloc : nullptr,
                                              o->near, o->n, R, field, far ? 1 : 0, cout, odt, out, s));

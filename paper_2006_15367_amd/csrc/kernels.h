@@ -113,5 +113,12 @@ hipError_t l2o_scatter(const float4 *pts, const int32_t *pt_leaf,
                        int R, int field, int far, int conj_out, int dtype,
                        void *out, hipStream_t s);
 
+// L2O + near + scatter for R >= 8 potentials: per leaf box an MFMA product of
+// the phase matrix [points x K] and the locals [K x R] (pt_start: leaf CSR).
+hipError_t l2o_leaf_mfma(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
+                         const int32_t *perm, const float4 *khat_w, int64_t K, float kw,
+                         const float2 *L, const float2 *near, int R, int conj_out, int dtype,
+                         void *out, hipStream_t s);
+
 }  // namespace dev
 }  // namespace mlfma

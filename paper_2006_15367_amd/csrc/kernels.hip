@@ -196,12 +196,117 @@ static hipError_t p2p_rc(const int2 *items, int64_t nitems, const float4 *pts,
     return hipGetLastError();
 }
 
+// P2P for 8..64 right-hand sides (potential) on the matrix cores: per work
+// item (a target leaf or a 64-point chunk of it), targets in tiles of 16 and
+// near sources in tiles of 64: the 256 threads build the Green's function
+// tile G[t][s] = e^{ikr}/r (0 for coincident points) in LDS, then wave w
+// multiplies it into right-hand sides 16w .. 16w+15 (columns) with the
+// sources as the reduction:  re += G_re q_re - G_im q_im,
+// im += G_re q_im + G_im q_re.  Source positions are moved into the target
+// leaf's frame exactly as in k_p2p.
+__global__ void __launch_bounds__(256)
+k_p2p_mfma(const int2 *__restrict__ items, const float4 *__restrict__ pts,
+           const int32_t *__restrict__ pt_start, const int32_t *__restrict__ near_start,
+           const int32_t *__restrict__ near_idx, const int32_t *__restrict__ coord, float leaf,
+           float kw, const float2 *__restrict__ qs, int R, float2 *__restrict__ out)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __shared__ float4 sp[64];
+    __shared__ int sid[64];
+    __shared__ float4 tp[16];
+    __shared__ float Gs[16 * 128];  // [target][G_re for 64 sources | G_im for 64 sources]
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, lr = lane & 15, lq = lane >> 4;
+    const int2 it = items[blockIdx.x];
+    const int b = it.x;
+    const int p0 = pt_start[b] + it.y;
+    const int nt = min(64, pt_start[b + 1] - p0);
+    const int cbx = coord[3 * b], cby = coord[3 * b + 1], cbz = coord[3 * b + 2];
+    const int e_beg = near_start[b], e_end = near_start[b + 1];
+    const int r = wave * 16 + lr;
+    const bool rv = r < R;
+    for (int t0 = 0; t0 < nt; t0 += 16) {
+        __syncthreads();
+        if (tid < 16) tp[tid] = t0 + tid < nt ? pts[p0 + t0 + tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+        f4 dre = {0.f, 0.f, 0.f, 0.f}, dim = dre;
+        int e = e_beg, j = e < e_end ? pt_start[near_idx[e]] : 0;
+        for (;;) {
+            // ---- the next tile of up to 64 near sources
+            __syncthreads();
+            int fill = 0;
+            while (fill < 64 && e < e_end) {
+                const int nb = near_idx[e];
+                const int j1 = pt_start[nb + 1];
+                const int cnt = min(64 - fill, j1 - j);
+                if (tid < cnt) {
+                    const float4 pj = pts[j + tid];
+                    sp[fill + tid] = make_float4(pj.x + (float)(coord[3 * nb] - cbx) * leaf,
+                                                 pj.y + (float)(coord[3 * nb + 1] - cby) * leaf,
+                                                 pj.z + (float)(coord[3 * nb + 2] - cbz) * leaf, 0.f);
+                    sid[fill + tid] = j + tid;
+                }
+                fill += cnt;
+                j += cnt;
+                if (j >= j1) {
+                    ++e;
+                    if (e < e_end) j = pt_start[near_idx[e]];
+                }
+            }
+            if (fill == 0) break;
+            __syncthreads();
+            for (int i = tid; i < 16 * 64; i += blockDim.x) {
+                const int t = i >> 6, sx = i & 63;
+                float gr = 0.f, gi = 0.f;
+                if (t0 + t < nt && sx < fill) {
+                    const float4 pi = tp[t], sj = sp[sx];
+                    const float dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float rinv = r2 > 0.f ? rsqrtf(r2) : 0.f;
+                    float sn, cs;
+                    __sincosf(kw * (r2 * rinv), &sn, &cs);
+                    gr = cs * rinv;
+                    gi = sn * rinv;
+                }
+                Gs[t * 128 + sx] = gr;
+                Gs[t * 128 + 64 + sx] = gi;
+            }
+            __syncthreads();
+            if (wave * 16 >= R) continue;
+            const float *Gr = Gs + lr * 128, *Gi = Gr + 64;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                const int sx = ks * 4 + lq;
+                const float2 x = (rv && sx < fill) ? qs[(int64_t)sid[sx] * R + r]
+                                                   : make_float2(0.f, 0.f);
+                const float ar = Gr[sx], ai = Gi[sx];
+                dre = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, x.x, dre, 0, 0, 0);
+                dre = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, -x.y, dre, 0, 0, 0);
+                dim = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, x.y, dim, 0, 0, 0);
+                dim = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, x.x, dim, 0, 0, 0);
+            }
+        }
+        if (rv) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = t0 + 4 * lq + v;
+                if (t < nt) out[(int64_t)(p0 + t) * R + r] = make_float2(dre[v], dim[v]);
+            }
+        }
+    }
+}
+
 hipError_t p2p(const int2 *items, int64_t nitems, const float4 *pts, const int32_t *pt_start,
                const int32_t *near_start, const int32_t *near_idx, const int32_t *coord,
                float leaf, float kw, const float2 *qs, int R, int field, float2 *out,
                hipStream_t s)
 {
     if (nitems == 0) return hipSuccess;
+    if (!field && R >= 8 && R <= 64) {
+        hipLaunchKernelGGL(k_p2p_mfma, dim3((unsigned)nitems), dim3(256), 0, s, items, pts,
+                           pt_start, near_start, near_idx, coord, leaf, kw, qs, R, out);
+        return hipGetLastError();
+    }
 #define P2P_RC(RCV) \
     return p2p_rc<RCV>(items, nitems, pts, pt_start, near_start, near_idx, coord, leaf, kw, qs, \
                        R, field, out, s)
@@ -264,11 +369,97 @@ k_c2m(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
     }
 }
 
+// C2M for 8..64 right-hand sides on the matrix cores: per leaf box
+// S[r][k] = sum_p F[p][k] q[p][r], F[p][k] = e^{-i kw khat_k.d_p}; rows are
+// samples (up to 12 tiles of 16), columns right-hand sides, the reduction
+// runs over the box's points in tiles of 16 (phase tile in LDS, shared by
+// the 4 waves; wave w takes right-hand sides 16w .. 16w+15).  Complex as
+// real MFMAs: re += F_re q_re - F_im q_im, im += F_re q_im + F_im q_re.
+constexpr int kC2mRowTiles = 12;
+
+__global__ void __launch_bounds__(256)
+k_c2m_mfma(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
+           const float4 *__restrict__ khat_w, int K, float kw, const float2 *__restrict__ qs,
+           int R, float2 *__restrict__ S)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    extern __shared__ float Fs[];  // [16][2K]: F_re in columns 0..K-1, F_im in K..2K-1
+    const int64_t b = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int p0 = pt_start[b], np = pt_start[b + 1] - p0;
+    const int nrt = (K + 15) / 16;
+    const int r = wave * 16 + lr;
+    const bool rv = r < R;
+    f4 dre[kC2mRowTiles], dim[kC2mRowTiles];
+#pragma unroll
+    for (int t = 0; t < kC2mRowTiles; ++t) dre[t] = dim[t] = f4{0.f, 0.f, 0.f, 0.f};
+    __shared__ float4 Pt[16];  // the points of the tile
+    for (int t0 = 0; t0 < np; t0 += 16) {
+        __syncthreads();
+        if (threadIdx.x < 16)
+            Pt[threadIdx.x] = t0 + (int)threadIdx.x < np ? pts[p0 + t0 + threadIdx.x]
+                                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+        // thread = sample k: one direction load, 16 phases from the staged points
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            const float4 kh = khat_w[k];
+#pragma unroll 4
+            for (int p = 0; p < 16; ++p) {
+                const float4 d = Pt[p];
+                float sn, cs;
+                __sincosf(-kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
+                const bool pv = t0 + p < np;
+                Fs[p * 2 * K + k] = pv ? cs : 0.f;
+                Fs[p * 2 * K + K + k] = pv ? sn : 0.f;
+            }
+        }
+        __syncthreads();
+        if (wave * 16 >= R) continue;
+#pragma unroll
+        for (int ps = 0; ps < 4; ++ps) {
+            const int p = ps * 4 + lq;
+            const float2 x = (rv && t0 + p < np) ? qs[(int64_t)(p0 + t0 + p) * R + r]
+                                                 : make_float2(0.f, 0.f);
+            const float *Fr = Fs + p * 2 * K, *Fi = Fr + K;
+#pragma unroll
+            for (int t = 0; t < kC2mRowTiles; ++t) {
+                if (t < nrt) {
+                    const int k = t * 16 + lr;
+                    const float ar = k < K ? Fr[k] : 0.f, ai = k < K ? Fi[k] : 0.f;
+                    dre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, x.x, dre[t], 0, 0, 0);
+                    dre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, -x.y, dre[t], 0, 0, 0);
+                    dim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, x.y, dim[t], 0, 0, 0);
+                    dim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, x.x, dim[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (!rv) return;
+    float2 *Sr = S + (b * R + r) * K;
+#pragma unroll
+    for (int t = 0; t < kC2mRowTiles; ++t) {
+        if (t < nrt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = t * 16 + 4 * lq + v;
+                if (k < K) Sr[k] = make_float2(dre[t][v], dim[t][v]);
+            }
+        }
+    }
+}
+
 hipError_t c2m(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
                const float4 *khat_w, int64_t K, float kw, const float2 *qs, int R,
                float2 *S, hipStream_t s)
 {
     if (nleaf == 0) return hipSuccess;
+    if (R >= 8 && R <= 64 && K <= 16 * kC2mRowTiles) {
+        const size_t lds = (size_t)16 * 2 * K * sizeof(float);
+        hipLaunchKernelGGL(k_c2m_mfma, dim3((unsigned)nleaf), dim3(256), lds, s, pts, pt_start,
+                           khat_w, (int)K, kw, qs, R, S);
+        return hipGetLastError();
+    }
     if (R == 1) {
         hipLaunchKernelGGL(k_c2m<1>, dim3((unsigned)nleaf, 1), dim3(256), 0, s, pts, pt_start,
                            khat_w, K, kw, qs, R, S);
@@ -400,6 +591,109 @@ __global__ void k_l2o_scatter(const float4 *__restrict__ pts,
     }
 }
 
+// L2O for many right-hand sides as a per-leaf product on the matrix cores:
+// far[p][r] = (i kw / 4 pi) sum_k E[p][k] L[b][r][k], E[p][k] = w_k e^{i kw khat.d_p}.
+// One workgroup per leaf box; its points in tiles of 16 rows.  The 4 waves
+// share the phase tile E (LDS, computed once per tile) and take chunks of 16
+// right-hand sides.  Complex product as real MFMAs: with x = L[r][k],
+//   re += E_re x_re - E_im x_im,  im += E_re x_im + E_im x_re,
+// so per k step two A fragments (E_re, E_im) and one complex load of L.
+// Lane l of v_mfma_f32_16x16x4_f32 feeds A[l%16][l/16], B[l/16][l%16] and
+// receives D[4(l/16)+v][l%16]: rows are points, columns right-hand sides.
+typedef float l2o_floatx4 __attribute__((ext_vector_type(4)));
+
+template <typename Tout>
+__global__ void __launch_bounds__(256)
+k_l2o_mfma(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
+           const int32_t *__restrict__ perm, const float4 *__restrict__ khat_w, int K, float kw,
+           const float2 *__restrict__ L, const float2 *__restrict__ near, int R, int conj_out,
+           Tout *__restrict__ out)
+{
+    extern __shared__ float Es[];  // [16][2K]: E_re in columns 0..K-1, E_im in K..2K-1
+    __shared__ float4 Pt[16];      // the points of the tile
+    const int64_t b = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int p0 = pt_start[b], np = pt_start[b + 1] - p0;
+    const int nchunk = (R + 15) / 16;
+    const float sc = kw * kInv4Pi;
+    for (int t0 = 0; t0 < np; t0 += 16) {
+        __syncthreads();
+        if (threadIdx.x < 16)
+            Pt[threadIdx.x] = t0 + (int)threadIdx.x < np ? pts[p0 + t0 + threadIdx.x]
+                                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+        // thread = sample k: one direction load, 16 phases from the staged points
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            const float4 kh = khat_w[k];
+#pragma unroll 4
+            for (int p = 0; p < 16; ++p) {
+                const float4 d = Pt[p];
+                float sn, cs;
+                __sincosf(kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
+                const bool pv = t0 + p < np;
+                Es[p * 2 * K + k] = pv ? cs * kh.w : 0.f;
+                Es[p * 2 * K + K + k] = pv ? sn * kh.w : 0.f;
+            }
+        }
+        __syncthreads();
+        const float *Ere = Es + lr * 2 * K, *Eim = Ere + K;
+        for (int ch = wave; ch < nchunk; ch += 4) {
+            const int r = ch * 16 + lr;
+            const bool rv = r < R;
+            const float2 *Lr = L + (b * R + (rv ? r : 0)) * K;
+            l2o_floatx4 dre = {0.f, 0.f, 0.f, 0.f}, dim = dre;
+            // the locals stream from L2 in batches of 8 k steps, the next
+            // batch in flight while the current one runs on the matrix cores
+            constexpr int B = 8;
+            float2 xa[B], xb[B];
+            auto load = [&](float2 (&x)[B], int kb) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int k = kb + 4 * u + lq;
+                    x[u] = (rv && k < K) ? Lr[k] : make_float2(0.f, 0.f);
+                }
+            };
+            auto run = [&](const float2 (&x)[B], int kb) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int k = kb + 4 * u + lq;
+                    const float are = k < K ? Ere[k] : 0.f, aim = k < K ? Eim[k] : 0.f;
+                    dre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, x[u].x, dre, 0, 0, 0);
+                    dre = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, -x[u].y, dre, 0, 0, 0);
+                    dim = __builtin_amdgcn_mfma_f32_16x16x4f32(are, x[u].y, dim, 0, 0, 0);
+                    dim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, x[u].x, dim, 0, 0, 0);
+                }
+            };
+            int kb = 0;
+            load(xa, 0);
+            for (; kb + 4 * B < K; kb += 8 * B) {
+                load(xb, kb + 4 * B);
+                run(xa, kb);
+                if (kb + 8 * B < K) load(xa, kb + 8 * B);
+                run(xb, kb + 4 * B);
+            }
+            if (kb < K) run(xa, kb);
+            if (!rv) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int p = t0 + 4 * lq + v;
+                if (p < np) {
+                    const int64_t sidx = p0 + p;
+                    // (i kw / 4 pi) (re + i im)
+                    float2 o = near[sidx * R + r];
+                    o.x += -sc * dim[v];
+                    o.y += sc * dre[v];
+                    if (conj_out) o.y = -o.y;
+                    Tout &dst = out[(int64_t)perm[sidx] * R + r];
+                    dst.x = o.x;
+                    dst.y = o.y;
+                }
+            }
+        }
+    }
+}
+
 template <int RC>
 static hipError_t l2o_rc(const float4 *pts, const int32_t *pt_leaf, const int32_t *perm,
                          const float4 *khat_w, int64_t K, float kw, const float2 *L,
@@ -417,6 +711,25 @@ static hipError_t l2o_rc(const float4 *pts, const int32_t *pt_leaf, const int32_
         if (field) L2O_LAUNCH(double2, true); else L2O_LAUNCH(double2, false);
     }
 #undef L2O_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t l2o_leaf_mfma(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
+                         const int32_t *perm, const float4 *khat_w, int64_t K, float kw,
+                         const float2 *L, const float2 *near, int R, int conj_out, int dtype,
+                         void *out, hipStream_t s)
+{
+    if (nleaf == 0) return hipSuccess;
+    const size_t lds = (size_t)16 * 2 * K * sizeof(float);
+    if (lds > 163840) return hipErrorInvalidValue;
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_l2o_mfma<float2>, dim3((unsigned)nleaf), dim3(256), lds, s, pts,
+                           pt_start, perm, khat_w, (int)K, kw, L, near, R, conj_out,
+                           (float2 *)out);
+    else
+        hipLaunchKernelGGL(k_l2o_mfma<double2>, dim3((unsigned)nleaf), dim3(256), lds, s, pts,
+                           pt_start, perm, khat_w, (int)K, kw, L, near, R, conj_out,
+                           (double2 *)out);
     return hipGetLastError();
 }
 

@@ -330,7 +330,7 @@ __device__ __forceinline__ void m2l_rec_parent(const char *Tsb, int lane8, int e
                                                const float2 *__restrict__ S, int64_t K, int R,
                                                int r0, int rc, int64_t kk, float2 (&acc)[8][RC])
 {
-    constexpr int U = 4;  // records in flight per wave
+    constexpr int U = RC >= 8 ? 2 : 4;  // records in flight per wave
     for (int eb = e0; eb < e1; eb += U) {
         float2 sv[U][RC];
 #pragma unroll
@@ -357,19 +357,21 @@ __device__ __forceinline__ void m2l_rec_parent(const char *Tsb, int lane8, int e
     }
 }
 
-template <int RC>
-__global__ void __launch_bounds__(1024)
+template <int RC, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ child_start,
           const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
           const int32_t *__restrict__ rec_off, const float2 *__restrict__ T,
           const float2 *__restrict__ S, int R, int nkc, int64_t ppb, float2 *__restrict__ Lout)
 {
-    // workgroup b serves sample chunk b % nkc and the contiguous parent range
-    // (b / nkc) * ppb ... + ppb; its 16 waves take those parents round-robin.
+    // workgroup w serves sample chunk w % nkc and the contiguous parent range
+    // (w / nkc) * ppb ... + ppb; its NW waves take those parents round-robin.
     // About one workgroup per CU, so the LDS staging of the operators is
-    // amortised over many parents.
+    // amortised over many parents.  (Numbering the workgroups so that each
+    // XCD gets a contiguous run of ranges measured slower at one RHS.)
     extern __shared__ float2 Ts[];  // [ntypes + 1][64], row ntypes = 0
-    const int kc = blockIdx.x % nkc;
+    const int64_t w = blockIdx.x;
+    const int kc = (int)(w % nkc);
     const int64_t k0 = (int64_t)kc * 64;
     stage_t_slice<64>(Ts, T, ntypes, K, k0);
     for (int idx = threadIdx.x; idx < 64; idx += blockDim.x)
@@ -383,9 +385,10 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
     const int64_t kk = valid ? k : K - 1;
     const int r0 = blockIdx.z * RC;
     const int rc = min(RC, R - r0);
-    const int64_t pbeg = (int64_t)(blockIdx.x / nkc) * ppb;
+    const int64_t pbeg = (w / nkc) * ppb;
     const int64_t pend = min(nparent, pbeg + ppb);
-    for (int64_t P = pbeg + (threadIdx.x >> 6); P < pend; P += 16) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t P = pbeg + wave; P < pend; P += NW) {
         const int o0 = __builtin_amdgcn_readfirstlane(child_start[P]);
         const int no = __builtin_amdgcn_readfirstlane(child_start[P + 1]) - o0;
         const int e0 = __builtin_amdgcn_readfirstlane(rec_start[P]);
@@ -423,21 +426,26 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
     if (nparent == 0 || K == 0) return hipSuccess;
     const size_t lds = (size_t)(ntypes + 1) * 64 * sizeof(float2);
     if (lds > 163840) return hipErrorInvalidValue;
+    // right-hand sides per thread: 1 or 4 (8 per thread, with 8 waves per
+    // workgroup for the registers of 8 x 8 accumulators, measured slower at
+    // 64 right-hand sides: 10.1 ms against 8.3 ms on the 262k sphere)
     const int RC = R == 1 ? 1 : 4;
+    const int NW = RC == 8 ? 8 : 16;
     const int nkc = (int)((K + 63) / 64);
     const int nz = (R + RC - 1) / RC;
-    // about one workgroup per CU (the LDS slice takes the CU), at least 16
-    // parents (one per wave) per workgroup
+    // about one workgroup per CU (the LDS slice takes the CU), at least one
+    // parent per wave per workgroup
     const int64_t per = std::max<int64_t>(1, std::min<int64_t>((256 + nkc * nz - 1) / (nkc * nz),
-                                                               (nparent + 15) / 16));
+                                                               (nparent + NW - 1) / NW));
     const int64_t ppb = (nparent + per - 1) / per;
     dim3 grid((unsigned)(nkc * ((nparent + ppb - 1) / ppb)), 1, (unsigned)nz);
-    if (RC == 1)
-        hipLaunchKernelGGL(k_m2l_rec<1>, grid, dim3(1024), lds, s, nparent, K, ntypes,
-                           child_start, rec_start, rec_src, rec_off, T, S, R, nkc, ppb, Lout);
-    else
-        hipLaunchKernelGGL(k_m2l_rec<4>, grid, dim3(1024), lds, s, nparent, K, ntypes,
-                           child_start, rec_start, rec_src, rec_off, T, S, R, nkc, ppb, Lout);
+#define M2L_REC(RCV, NWV)                                                                      \
+    hipLaunchKernelGGL((k_m2l_rec<RCV, NWV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
+                       child_start, rec_start, rec_src, rec_off, T, S, R, nkc, ppb, Lout)
+    if (RC == 1) M2L_REC(1, 16);
+    else if (RC == 4) M2L_REC(4, 16);
+    else M2L_REC(8, 8);
+#undef M2L_REC
     return hipGetLastError();
 }
 

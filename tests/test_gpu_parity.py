@@ -209,7 +209,13 @@ def test_bf16x3_interpolation_accuracy(c1):
 
 
 def test_batched_64_rhs_equals_single():
-    """64 right-hand sides in one call equal 64 single-RHS calls."""
+    """64 right-hand sides in one call equal 64 single-RHS calls.
+
+    The batched call runs C2M and L2O as per-leaf MFMA products (R >= 8),
+    the single-RHS calls as per-point loops: the same FP32 arithmetic summed
+    in another order.  Rounding (2^-24 per operation) grows with the
+    cancellation in the far-field sums, so the bound is 1e-5, two orders
+    below the method's 1e-3; the dense check pins the batched values."""
     torch = cuda_or_skip()
     from paper_2006_15367_amd import mlfma as G
     xyz, Q = W.make("sphere262k_r64", n=32768)
@@ -225,8 +231,19 @@ def test_batched_64_rhs_equals_single():
         p = ops.matvec(torch.from_numpy(np.ascontiguousarray(Q[:, r])).cuda())
         a = ops.adjoint(torch.from_numpy(np.ascontiguousarray(Q[:, r])).cuda())
         torch.cuda.synchronize()
-        assert rel_l2(P[:, r], p.cpu().numpy()) < 1e-6
-        assert rel_l2(A[:, r], a.cpu().numpy()) < 1e-6
+        e_p = rel_l2(P[:, r], p.cpu().numpy())
+        e_a = rel_l2(A[:, r], a.cpu().numpy())
+        say("rhs", r, "batched vs single: matvec", e_p, "adjoint", e_a)
+        assert e_p < 1e-5
+        assert e_a < 1e-5
+    # the batched values against the dense definition on sampled targets
+    from oracle import dense
+    rng = np.random.default_rng(5)
+    idx = rng.choice(xyz.shape[0], 256, replace=False)
+    ref = dense.potential(xyz, np.ascontiguousarray(Q[:, :4]).astype(np.complex128), K, tgt=xyz[idx])
+    e_d = rel_l2(P[idx, :4], ref)
+    say("batched vs dense (256 targets, 4 rhs)", e_d)
+    assert e_d < 1e-3
 
 
 def test_graph_replays_match_eager(c1):
