@@ -331,28 +331,46 @@ __device__ __forceinline__ void m2l_rec_parent(const char *Tsb, int lane8, int e
                                                int r0, int rc, int64_t kk, float2 (&acc)[8][RC])
 {
     constexpr int U = RC >= 8 ? 2 : 4;  // records in flight per wave
+    // the scalar record data of the next U records is loaded while the
+    // current ones compute (one scalar-load latency per U records)
+    int src[U], off[U][NO];
+    auto load_rec = [&](int eb, int (&sr)[U], int (&of)[U][NO]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = eb + u < e1 ? eb + u : e1 - 1;
+            sr[u] = rec_src[e];
+#pragma unroll
+            for (int i = 0; i < NO; ++i) of[u][i] = rec_off[8 * e + i];
+        }
+    };
+    load_rec(e0, src, off);
     for (int eb = e0; eb < e1; eb += U) {
         float2 sv[U][RC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = eb + u < e1 ? eb + u : e0;
-            const int64_t s = __builtin_amdgcn_readfirstlane(rec_src[e]);
-            const float2 *Sr = S + (s * R + r0) * K;
+            const float2 *Sr = S + ((int64_t)src[u] * R + r0) * K + kk;
 #pragma unroll
             for (int c = 0; c < RC; ++c)
-                sv[u][c] = c < rc ? Sr[c * K + kk] : make_float2(0.f, 0.f);
+                sv[u][c] = (RC == 1 || c < rc) ? Sr[c * K] : make_float2(0.f, 0.f);
         }
+        int nsrc[U], noff[U][NO];
+        load_rec(eb + U < e1 ? eb + U : eb, nsrc, noff);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (eb + u < e1) {
-                const int32_t *off = rec_off + 8 * (int64_t)(eb + u);
 #pragma unroll
                 for (int i = 0; i < NO; ++i) {
-                    const float2 tv = *(const float2 *)(Tsb + (__builtin_amdgcn_readfirstlane(off[i]) + lane8));
+                    const float2 tv = *(const float2 *)(Tsb + (off[u][i] + lane8));
 #pragma unroll
                     for (int c = 0; c < RC; ++c) acc[i][c] = cfma(tv, sv[u][c], acc[i][c]);
                 }
             }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            src[u] = nsrc[u];
+#pragma unroll
+            for (int i = 0; i < NO; ++i) off[u][i] = noff[u][i];
         }
     }
 }
