@@ -83,11 +83,15 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b)
 }
 
 // Compile-time shape of one level pair and direction.  LC, LP: bands of
-// the child and parent levels; BW children per item; NW waves per group.
-template <int LC, int LP, bool DOWN_, int BW_, int NW_>
+// the child and parent levels; BW children per item; NW waves per group;
+// MINW resident waves per SIMD.
+template <int LC, int LP, bool DOWN_, int BW_, int NW_, int MINW_>
 struct Shape {
     static constexpr bool DOWN = DOWN_;
     static constexpr int BW = BW_, NW = NW_;
+    // resident waves per SIMD asked of the register allocator (two
+    // workgroups per CU where the LDS plan allows it)
+    static constexpr int MINW = MINW_;
     static constexpr int LI = DOWN ? LP : LC, LO = DOWN ? LC : LP;
     static constexpr int TI = LI + 1, PI = 2 * LI + 2, TO = LO + 1, PO = 2 * LO + 2;
     static constexpr int M = 2 * LC + 1, NM = LC + 1;
@@ -131,7 +135,7 @@ struct Shape {
 };
 
 template <class S>
-__global__ void __launch_bounds__(64 * S::NW)
+__global__ void __launch_bounds__(64 * S::NW, S::MINW)
 k_onepass(const float2 *__restrict__ In, const int32_t *__restrict__ child_start,
           const uint8_t *__restrict__ child_oct, const float *__restrict__ F,
           const float *__restrict__ Am, const float *__restrict__ G,
@@ -178,17 +182,9 @@ k_onepass(const float2 *__restrict__ In, const int32_t *__restrict__ child_start
     float *R2 = W1;            // L2L: output staging [b][KOUT][2]
     const float2 *Ez = Es + 2 * S::THP * S::EP;
 
-    // operator fragments of s1 (F^T) and s3 (G^T) in registers
-    float a1[S::RT1][S::KS1], a3[S::RT3][S::KS3];
-#pragma unroll
-    for (int rt = 0; rt < S::RT1; ++rt)
-#pragma unroll
-        for (int ks = 0; ks < S::KS1; ++ks) a1[rt][ks] = Fs[(ks * 4 + lq) * S::R1 + rt * 16 + lr];
-#pragma unroll
-    for (int rt = 0; rt < S::RT3; ++rt)
-#pragma unroll
-        for (int ks = 0; ks < S::KS3; ++ks)
-            a3[rt][ks] = Gs[(ks * 4 + lq) * (16 * S::RT3) + rt * 16 + lr];
+    // operator fragments of s1 (F^T) and s3 (G^T), read from LDS per use
+    const float *a1p = Fs + lq * S::R1 + lr;
+    const float *a3p = Gs + lq * (16 * S::RT3) + lr;
 
     const int64_t ntasks = nparent * R;
     const int64_t stride = (int64_t)gridDim.x * S::NW;
@@ -284,7 +280,8 @@ k_onepass(const float2 *__restrict__ In, const int32_t *__restrict__ child_start
                 for (int ks = 0; ks < S::KS1; ++ks) {
                     const float bv = xb[8 * ks];
 #pragma unroll
-                    for (int rt = 0; rt < S::RT1; ++rt) d[rt] = mma(a1[rt][ks], bv, d[rt]);
+                    for (int rt = 0; rt < S::RT1; ++rt)
+                        d[rt] = mma(a1p[4 * ks * S::R1 + rt * 16], bv, d[rt]);
                 }
             } else {
                 const int oc = __shfl(oct_lane, b, 64);
@@ -301,7 +298,8 @@ k_onepass(const float2 *__restrict__ In, const int32_t *__restrict__ child_start
                     const float2 z = cmulf(cmulf(ex, ey), cmulf(ez, X[e]));
                     const float bv = part ? z.y : z.x;
 #pragma unroll
-                    for (int rt = 0; rt < S::RT1; ++rt) d[rt] = mma(a1[rt][ks], bv, d[rt]);
+                    for (int rt = 0; rt < S::RT1; ++rt)
+                        d[rt] = mma(a1p[4 * ks * S::R1 + rt * 16], bv, d[rt]);
                 }
             }
 #pragma unroll
@@ -354,11 +352,14 @@ k_onepass(const float2 *__restrict__ In, const int32_t *__restrict__ child_start
             const float *yb = Y2 + b * S::YB + lq * S::P2 + lr;
 #pragma unroll
             for (int ks = 0; ks < S::KS3; ++ks) {
+                float av[S::RT3];
+#pragma unroll
+                for (int rt = 0; rt < S::RT3; ++rt) av[rt] = a3p[4 * ks * 16 * S::RT3 + rt * 16];
 #pragma unroll
                 for (int t = 0; t < S::CT3; ++t) {
                     const float bv = yb[4 * ks * S::P2 + t * 16];
 #pragma unroll
-                    for (int rt = 0; rt < S::RT3; ++rt) d[t][rt] = mma(a3[rt][ks], bv, d[t][rt]);
+                    for (int rt = 0; rt < S::RT3; ++rt) d[t][rt] = mma(av[rt], bv, d[t][rt]);
                 }
             }
             const int oc = __shfl(oct_lane, b, 64);
@@ -464,9 +465,9 @@ hipError_t dispatch(int Lc, int Lp, const float2 *In, const int32_t *cs, const u
                     float2 *Out, int64_t nparent, int R, hipStream_t st)
 {
     if (Lc == 8 && Lp == 13)
-        return launch_shape<Shape<8, 13, DOWN, 1, 8>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
+        return launch_shape<Shape<8, 13, DOWN, 1, 8, 4>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
     if (Lc == 13 && Lp == 20)
-        return launch_shape<Shape<13, 20, DOWN, 1, 8>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
+        return launch_shape<Shape<13, 20, DOWN, 1, 8, 2>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
     return hipErrorInvalidValue;
 }
 
