@@ -69,7 +69,7 @@ struct mlfma_ops_s {
     int32_t *perm = nullptr, *pt_leaf = nullptr, *pt_start = nullptr;
     int32_t *near_start = nullptr, *near_idx = nullptr, *leaf_coord = nullptr;
     int2 *p2p_items = nullptr;       // (leaf, first target) per 64-target chunk
-    int64_t n_p2p_items = 0;
+    int64_t n_p2p_items = 0, n_p2p_heavy = 0;
     float2 *qs = nullptr, *near = nullptr;
     float2 *fq = nullptr, *fg = nullptr;  // fields for the position gradient [n][R][3]
     float2 *X1 = nullptr, *X2 = nullptr;
@@ -431,7 +431,7 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
         LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, cin, o->qs, s));
         const int64_t nnear = o->n * R * (field ? 3 : 1);
         if (parts & MLFMA_NEAR)
-            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->pts, o->pt_start,
+            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->n_p2p_heavy, o->pts, o->pt_start,
                                          o->near_start, o->near_idx, o->leaf_coord,
                                          (float)o->tree->leaf, (float)o->k, o->qs, R, field,
                                          o->near, s));
@@ -632,10 +632,23 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         if ((r = upload(o, &o->near_start, v32.data(), (int64_t)v32.size()))) return r;
         if ((r = upload(o, &o->near_idx, t->near_idx.data(), (int64_t)t->near_idx.size()))) return r;
         if ((r = upload(o, &o->leaf_coord, t->lev[nl].coord.data(), 3 * nleaf))) return r;
-        std::vector<int2> items;
-        for (int64_t b = 0; b < nleaf; ++b)
-            for (int64_t t0 = 0; t0 < t->pt_start[b + 1] - t->pt_start[b]; t0 += 64)
-                items.push_back(make_int2((int)b, (int)t0));
+        // P2P work items, heavy ones (many target x source pairs: dense
+        // leaves) first; those run with four waves per item
+        std::vector<int2> items, light;
+        for (int64_t b = 0; b < nleaf; ++b) {
+            int64_t nsrc = 0;
+            for (int64_t e = t->near_start[b]; e < t->near_start[b + 1]; ++e) {
+                const int32_t nb = t->near_idx[e];
+                nsrc += t->pt_start[nb + 1] - t->pt_start[nb];
+            }
+            const int64_t np = t->pt_start[b + 1] - t->pt_start[b];
+            for (int64_t t0 = 0; t0 < np; t0 += 64) {
+                const int64_t nt = std::min<int64_t>(64, np - t0);
+                (nt * nsrc >= (int64_t)1 << 15 ? items : light).push_back(make_int2((int)b, (int)t0));
+            }
+        }
+        o->n_p2p_heavy = (int64_t)items.size();
+        items.insert(items.end(), light.begin(), light.end());
         o->n_p2p_items = (int64_t)items.size();
         if ((r = upload(o, &o->p2p_items, items.data(), o->n_p2p_items))) return r;
         if ((r = dalloc(o, &o->qs, t->n * R))) return r;

@@ -17,8 +17,9 @@ hipError_t zero(float2 *p, int64_t count, hipStream_t s);
 
 // near-field potential (field = 0) or gradient (field = 1) in sorted order:
 // out [n][R] or [n][R][3]; items[w] = (leaf, first target offset) covers up
-// to 64 targets of that leaf
-hipError_t p2p(const int2 *items, int64_t nitems, const float4 *pts,
+// to 64 targets of that leaf; the first nheavy items (dense leaves) run with
+// four waves per item
+hipError_t p2p(const int2 *items, int64_t nitems, int64_t nheavy, const float4 *pts,
                const int32_t *pt_start, const int32_t *near_start, const int32_t *near_idx,
                const int32_t *leaf_coord, float leaf, float kw, const float2 *qs, int R,
                int field, float2 *out, hipStream_t s);

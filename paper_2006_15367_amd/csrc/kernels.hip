@@ -60,15 +60,17 @@ hipError_t zero(float2 *p, int64_t count, hipStream_t s)
 }
 
 // ------------------------------------------------------------------- P2P --
-// One single-wave workgroup per work item (a target leaf, or a chunk of 64
+// One workgroup of NW waves per work item (a target leaf, or a chunk of 64
 // of its points).  The near sources are staged in LDS in batches of 256,
 // their positions moved into the target leaf's frame (leaf-local offset +
 // exact integer leaf offset x leaf side, which keeps FP32 accuracy for close
-// pairs far from the origin).  With nt targets the lanes form G = 64/T groups
-// (T = nt rounded up to a power of two): lane (g, t) takes target t and every
-// G-th staged source; the G partial sums are added with cross-lane shuffles.
-template <int RC, bool FIELD>
-__global__ void __launch_bounds__(64)
+// pairs far from the origin).  With nt targets the 64 NW lanes form
+// G = 64 NW / T groups (T = nt rounded up to a power of two): lane (g, t)
+// takes target t and every G-th staged source; the partial sums of a target
+// are added with cross-lane shuffles inside each wave and through LDS across
+// the waves (fixed order, so the result does not depend on timing).
+template <int RC, bool FIELD, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
       const int32_t *__restrict__ pt_start, const int32_t *__restrict__ near_start,
       const int32_t *__restrict__ near_idx, const int32_t *__restrict__ coord, float leaf,
@@ -76,17 +78,18 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
 {
     constexpr int NA = FIELD ? 3 : 1;
     constexpr int CH = 256;
+    constexpr int NT = 64 * NW;
     __shared__ float4 sp[CH];
     __shared__ float2 sq[CH * RC];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int2 it = items[blockIdx.x];
     const int b = it.x;
     const int p0 = pt_start[b];
     const int nt = min(64, pt_start[b + 1] - p0 - it.y);
     int Tp = 1;
     while (Tp < nt) Tp <<= 1;
-    const int G = 64 / Tp;
-    const int t = lane & (Tp - 1), g = lane / Tp;
+    const int G = NT / Tp;
+    const int t = tid & (Tp - 1), g = tid / Tp;
     const bool tv = t < nt;
     const int i = p0 + it.y + (tv ? t : 0);
     const int r0 = blockIdx.y * RC;
@@ -134,6 +137,7 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
         __syncthreads();
     };
 
+    // stage the near sources, 64 NW at a time
     int fill = 0;
     const int e1 = near_start[b + 1];
     for (int e = near_start[b]; e < e1; ++e) {
@@ -142,25 +146,32 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
         const float oy = (float)(coord[3 * nb + 1] - cby) * leaf;
         const float oz = (float)(coord[3 * nb + 2] - cbz) * leaf;
         const int j1 = pt_start[nb + 1];
-        for (int j = pt_start[nb]; j < j1; j += 64) {
-            const int cnt = min(64, j1 - j);
-            if (fill + cnt > CH) {
-                process(fill);
-                fill = 0;
-            }
-            if (lane < cnt) {
-                const float4 pj = pts[j + lane];
-                sp[fill + lane] = make_float4(pj.x + ox, pj.y + oy, pj.z + oz, 0.f);
+        for (int j = pt_start[nb]; j < j1; j += NT) {
+            const int cnt = min(NT, j1 - j);
+            int done = 0;
+            while (done < cnt) {
+                const int take = min(cnt - done, CH - fill);
+                if (tid < take) {
+                    const float4 pj = pts[j + done + tid];
+                    sp[fill + tid] = make_float4(pj.x + ox, pj.y + oy, pj.z + oz, 0.f);
 #pragma unroll
-                for (int c = 0; c < RC; ++c)
-                    sq[(fill + lane) * RC + c] =
-                        c < rc ? qs[(int64_t)(j + lane) * R + r0 + c] : make_float2(0.f, 0.f);
+                    for (int c = 0; c < RC; ++c)
+                        sq[(fill + tid) * RC + c] = c < rc ? qs[(int64_t)(j + done + tid) * R + r0 + c]
+                                                           : make_float2(0.f, 0.f);
+                }
+                fill += take;
+                done += take;
+                if (fill == CH) {
+                    process(fill);
+                    fill = 0;
+                }
             }
-            fill += cnt;
         }
     }
     process(fill);
-    // add the G partial sums of each target (lanes t, t+T, t+2T, ...)
+    // add the G partial sums of each target: lanes t, t+T, ... inside a wave
+    // by shuffles, then the waves through LDS
+    const int GW = Tp < 64 ? 64 / Tp : 1;  // groups per wave
     for (int sft = Tp; sft < 64; sft <<= 1) {
 #pragma unroll
         for (int c = 0; c < RC; ++c)
@@ -170,7 +181,35 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
                 acc[c][a].y += __shfl_xor(acc[c][a].y, sft, 64);
             }
     }
-    if (g == 0 && tv) {
+    (void)GW;
+    if (NW > 1) {
+        // after the shuffles, lane t (< Tp, < 64) of every wave holds that
+        // wave's sum for target t (Tp <= 64); with Tp = 64 each wave holds
+        // one group's sum per lane
+        __shared__ float2 red[NW * 64 * RC * NA];  // [NW][64][RC][NA]
+        const int wv = tid >> 6, ln = tid & 63;
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) red[((wv * 64 + ln) * RC + c) * NA + a] = acc[c][a];
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+#pragma unroll
+                for (int a = 0; a < NA; ++a) {
+                    float2 v = red[(ln * RC + c) * NA + a];
+                    for (int w = 1; w < NW; ++w) {
+                        const float2 u = red[((w * 64 + ln) * RC + c) * NA + a];
+                        v.x += u.x;
+                        v.y += u.y;
+                    }
+                    acc[c][a] = v;
+                }
+        }
+    }
+    // lane t < Tp of wave 0 now holds the total of target t
+    if (tid < Tp && tv) {
 #pragma unroll
         for (int c = 0; c < RC; ++c)
             if (c < rc)
@@ -180,19 +219,35 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
     }
 }
 
+template <int RC, int NW>
+static void p2p_launch(const int2 *items, int64_t nitems, const float4 *pts,
+                       const int32_t *pt_start, const int32_t *near_start,
+                       const int32_t *near_idx, const int32_t *coord, float leaf, float kw,
+                       const float2 *qs, int R, int field, float2 *out, hipStream_t s)
+{
+    if (nitems == 0) return;
+    dim3 grid((unsigned)nitems, (R + RC - 1) / RC);
+    if (field)
+        hipLaunchKernelGGL((k_p2p<RC, true, NW>), grid, dim3(64 * NW), 0, s, items, pts,
+                           pt_start, near_start, near_idx, coord, leaf, kw, qs, R, out);
+    else
+        hipLaunchKernelGGL((k_p2p<RC, false, NW>), grid, dim3(64 * NW), 0, s, items, pts,
+                           pt_start, near_start, near_idx, coord, leaf, kw, qs, R, out);
+}
+
+// heavy items (dense leaves: hundreds of points) with four waves each, the
+// rest with one
 template <int RC>
-static hipError_t p2p_rc(const int2 *items, int64_t nitems, const float4 *pts,
+static hipError_t p2p_rc(const int2 *items, int64_t nitems, int64_t nheavy, const float4 *pts,
                          const int32_t *pt_start, const int32_t *near_start,
                          const int32_t *near_idx, const int32_t *coord, float leaf, float kw,
                          const float2 *qs, int R, int field, float2 *out, hipStream_t s)
 {
-    dim3 grid((unsigned)nitems, (R + RC - 1) / RC);
-    if (field)
-        hipLaunchKernelGGL((k_p2p<RC, true>), grid, dim3(64), 0, s, items, pts, pt_start,
-                           near_start, near_idx, coord, leaf, kw, qs, R, out);
-    else
-        hipLaunchKernelGGL((k_p2p<RC, false>), grid, dim3(64), 0, s, items, pts, pt_start,
-                           near_start, near_idx, coord, leaf, kw, qs, R, out);
+    constexpr int NWH = RC <= 4 ? 4 : 1;
+    p2p_launch<RC, NWH>(items, nheavy, pts, pt_start, near_start, near_idx, coord, leaf, kw, qs,
+                        R, field, out, s);
+    p2p_launch<RC, 1>(items + nheavy, nitems - nheavy, pts, pt_start, near_start, near_idx,
+                      coord, leaf, kw, qs, R, field, out, s);
     return hipGetLastError();
 }
 
@@ -296,7 +351,8 @@ k_p2p_mfma(const int2 *__restrict__ items, const float4 *__restrict__ pts,
     }
 }
 
-hipError_t p2p(const int2 *items, int64_t nitems, const float4 *pts, const int32_t *pt_start,
+hipError_t p2p(const int2 *items, int64_t nitems, int64_t nheavy, const float4 *pts,
+               const int32_t *pt_start,
                const int32_t *near_start, const int32_t *near_idx, const int32_t *coord,
                float leaf, float kw, const float2 *qs, int R, int field, float2 *out,
                hipStream_t s)
@@ -308,8 +364,8 @@ hipError_t p2p(const int2 *items, int64_t nitems, const float4 *pts, const int32
         return hipGetLastError();
     }
 #define P2P_RC(RCV) \
-    return p2p_rc<RCV>(items, nitems, pts, pt_start, near_start, near_idx, coord, leaf, kw, qs, \
-                       R, field, out, s)
+    return p2p_rc<RCV>(items, nitems, nheavy, pts, pt_start, near_start, near_idx, coord, leaf, \
+                       kw, qs, R, field, out, s)
     if (R == 1) P2P_RC(1);
     if (R == 2) P2P_RC(2);
     if (R <= 4) P2P_RC(4);
