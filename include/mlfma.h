@@ -287,7 +287,8 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * Diagnostics: the kernel variant the autotuner chose for each level
  * (out[l-1] for levels 1..n_levels; -1 where a level has no such kernel).
  * kernel = MLFMA_K_M2L: 0 per-observer lists from L2, 1 operators staged in
- * LDS, 2 sibling groups, 3 sibling groups with per-source records.
+ * LDS, 2 sibling groups, 3 sibling groups with per-source records, 4 the
+ * same with a slice-major sweep (for many right-hand sides).
  * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
  * and l+1, -1 on the leaf level and above level 3): 0 three passes through
  * HBM (ids _S1.._S3), 1 one pass with the intermediates in LDS.

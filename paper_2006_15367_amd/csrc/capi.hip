@@ -40,7 +40,8 @@ struct DevLevel {
     int32_t *base = nullptr;         // 49 cx + 7 cy + cz
     int16_t *typemap = nullptr;      // [343] offset code -> operator or -1
     int m2l_variant = 0;             // 0 per-observer (L2), 1 operators in LDS, 2 sibling groups,
-                                     // 3 sibling groups with per-source records
+                                     // 3 sibling groups with per-source records, 4 = 3 with
+                                     // the slice-major sweep
     int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     float2 *S = nullptr, *Lloc = nullptr;  // [nbox][R][K]
@@ -243,8 +244,9 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s)
         return dev::m2l_sg(Pl.nbox, D.K, D.ntypes, Pl.child_start, Pl.nbr_start, Pl.nbr_idx,
                            D.base, D.typemap, D.T, D.S, R, D.Lloc, s);
     case 3:
+    case 4:
         return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
-                            D.rec_off, D.T, D.S, R, D.Lloc, s);
+                            D.rec_off, D.T, D.S, R, D.Lloc, s, variant == 4);
     default:
         return dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s);
     }
@@ -326,7 +328,7 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 5; ++v) {
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -958,7 +960,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-        if (variant < 0 || variant > 3) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant < 0 || variant > 4) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         o->lev[level].m2l_variant = variant;
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)

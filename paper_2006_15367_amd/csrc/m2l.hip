@@ -380,16 +380,26 @@ __global__ void __launch_bounds__(64 * NW)
 k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ child_start,
           const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
           const int32_t *__restrict__ rec_off, const float2 *__restrict__ T,
-          const float2 *__restrict__ S, int R, int nkc, int64_t ppb, float2 *__restrict__ Lout)
+          const float2 *__restrict__ S, int R, int nkc, int64_t ppb, int nwg,
+          float2 *__restrict__ Lout)
 {
-    // workgroup w serves sample chunk w % nkc and the contiguous parent range
-    // (w / nkc) * ppb ... + ppb; its NW waves take those parents round-robin.
-    // About one workgroup per CU, so the LDS staging of the operators is
-    // amortised over many parents.  (Numbering the workgroups so that each
-    // XCD gets a contiguous run of ranges measured slower at one RHS.)
+    // Two schedules (about one workgroup per CU either way, so the LDS
+    // staging of the operators is amortised over many parents):
+    //  nwg == 0: workgroup w serves sample chunk w % nkc, right-hand-side
+    //    chunk blockIdx.z and the contiguous parent range (w / nkc) * ppb
+    //    ... + ppb; its NW waves take those parents round-robin.  (Numbering
+    //    the workgroups so that each XCD gets a contiguous run of ranges
+    //    measured slower at one RHS.)
+    //  nwg > 0: slice-major sweep for many right-hand sides.  The nwg
+    //    workgroups of one (sample chunk, RHS chunk) slice are consecutive,
+    //    so the resident workgroups share a slice and sweep the parents
+    //    interleaved (parent = (w nwg ... ) + wave): the sources they re-read
+    //    stay within one window of the Morton order, small enough for the
+    //    Infinity Cache, instead of every slice streaming at once.
     extern __shared__ float2 Ts[];  // [ntypes + 1][64], row ntypes = 0
-    const int64_t w = blockIdx.x;
-    const int kc = (int)(w % nkc);
+    const int64_t w = nwg ? blockIdx.x % nwg : blockIdx.x;
+    const int64_t slice = nwg ? blockIdx.x / nwg : 0;
+    const int kc = nwg ? (int)(slice % nkc) : (int)(w % nkc);
     const int64_t k0 = (int64_t)kc * 64;
     stage_t_slice<64>(Ts, T, ntypes, K, k0);
     for (int idx = threadIdx.x; idx < 64; idx += blockDim.x)
@@ -401,12 +411,13 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
     const int64_t k = k0 + lane;
     const bool valid = k < K;
     const int64_t kk = valid ? k : K - 1;
-    const int r0 = blockIdx.z * RC;
+    const int r0 = (nwg ? (int)(slice / nkc) : (int)blockIdx.z) * RC;
     const int rc = min(RC, R - r0);
-    const int64_t pbeg = (w / nkc) * ppb;
-    const int64_t pend = min(nparent, pbeg + ppb);
+    const int64_t pbeg = nwg ? w * NW : (w / nkc) * ppb;
+    const int64_t pend = nwg ? nparent : min(nparent, pbeg + ppb);
+    const int64_t pstep = nwg ? (int64_t)nwg * NW : NW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t P = pbeg + wave; P < pend; P += NW) {
+    for (int64_t P = pbeg + wave; P < pend; P += pstep) {
         const int o0 = __builtin_amdgcn_readfirstlane(child_start[P]);
         const int no = __builtin_amdgcn_readfirstlane(child_start[P + 1]) - o0;
         const int e0 = __builtin_amdgcn_readfirstlane(rec_start[P]);
@@ -439,7 +450,8 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
 
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
-                   const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s)
+                   const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
+                   bool sweep)
 {
     if (nparent == 0 || K == 0) return hipSuccess;
     const size_t lds = (size_t)(ntypes + 1) * 64 * sizeof(float2);
@@ -448,21 +460,28 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
     // workgroup for the registers of 8 x 8 accumulators, measured slower at
     // 64 right-hand sides: 10.1 ms against 8.3 ms on the 262k sphere)
     const int RC = R == 1 ? 1 : 4;
-    const int NW = RC == 8 ? 8 : 16;
+    const int NW = 16;
     const int nkc = (int)((K + 63) / 64);
     const int nz = (R + RC - 1) / RC;
-    // about one workgroup per CU (the LDS slice takes the CU), at least one
-    // parent per wave per workgroup
-    const int64_t per = std::max<int64_t>(1, std::min<int64_t>((256 + nkc * nz - 1) / (nkc * nz),
-                                                               (nparent + NW - 1) / NW));
-    const int64_t ppb = (nparent + per - 1) / per;
-    dim3 grid((unsigned)(nkc * ((nparent + ppb - 1) / ppb)), 1, (unsigned)nz);
+    dim3 grid;
+    int64_t ppb = 0;
+    int nwg = 0;
+    if (sweep) {
+        // one workgroup per CU per slice, slices one after the other
+        nwg = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nparent + NW - 1) / NW));
+        grid = dim3((unsigned)(nwg * nkc * nz), 1, 1);
+    } else {
+        // about one workgroup per CU in all, at least one parent per wave
+        const int64_t per = std::max<int64_t>(
+            1, std::min<int64_t>((256 + nkc * nz - 1) / (nkc * nz), (nparent + NW - 1) / NW));
+        ppb = (nparent + per - 1) / per;
+        grid = dim3((unsigned)(nkc * ((nparent + ppb - 1) / ppb)), 1, (unsigned)nz);
+    }
 #define M2L_REC(RCV, NWV)                                                                      \
     hipLaunchKernelGGL((k_m2l_rec<RCV, NWV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
-                       child_start, rec_start, rec_src, rec_off, T, S, R, nkc, ppb, Lout)
+                       child_start, rec_start, rec_src, rec_off, T, S, R, nkc, ppb, nwg, Lout)
     if (RC == 1) M2L_REC(1, 16);
-    else if (RC == 4) M2L_REC(4, 16);
-    else M2L_REC(8, 8);
+    else M2L_REC(4, 16);
 #undef M2L_REC
     return hipGetLastError();
 }

@@ -142,21 +142,29 @@ def test_field_vs_dense(c1):
     assert e < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_every_m2l_variant(c1, variant):
     torch = c1["torch"]
     say("c1: M2L variant", variant)
     qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
     ops = c1["gops"]
     chosen = ops.variants("m2l")
+    n = c1["xyz"].shape[0]
+    rng = np.random.default_rng(40 + variant)
+    Q = np.empty((n, 4), np.complex64)
+    Q[:, 0] = c1["q"]
+    Q[:, 1:] = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
     try:
         for l in range(3, c1["ot"].n_lev + 1):
             ops.set_variant(l, variant)
         phi = _run(c1, ops.matvec, qd)
+        P = _run(c1, ops.matvec, torch.from_numpy(Q).cuda())
     finally:
         for l in range(3, c1["ot"].n_lev + 1):
             ops.set_variant(l, chosen[l - 1])
     assert rel_l2(phi, c1["ophi"]) < 1e-4
+    # the same variant with four right-hand sides at once
+    assert rel_l2(P[:, 0], phi) < 1e-5
 
 
 @pytest.mark.parametrize("variant", [0, 1])
