@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--bf16x3", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="capture the matvec into a HIP graph and replay it")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="every kernel on the caller's stream (no near/far overlap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
@@ -210,7 +212,7 @@ def main():
     tree = G.Tree(xyz, W.LEAF_SIZE)
     t1 = time.perf_counter()
     ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=args.bf16x3,
-                      graph=args.graph)
+                      graph=args.graph, one_stream=args.one_stream)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     tinfo = tree.info()
@@ -290,6 +292,7 @@ def main():
                     "ms_per_step": round(adj_ms, 4)},
         "setup_s": {"tree": round(t1 - t0, 3), "operators": round(t2 - t1, 3)},
         "graph": bool(args.graph),
+        "one_stream": bool(args.one_stream),
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
         "m2l_variant_per_level": ops.variants("m2l"),

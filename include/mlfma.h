@@ -72,10 +72,15 @@ enum mlfma_flags {
                                 (hi*hi + hi*lo + lo*hi, FP32 accumulation)  */
     MLFMA_NO_AUTOTUNE = 2,   /* skip the kernel-variant timing at precompute
                                 (variants differ only in summation order)   */
-    MLFMA_USE_GRAPH = 4      /* capture each distinct call (buffers, nrhs,
+    MLFMA_USE_GRAPH = 4,     /* capture each distinct call (buffers, nrhs,
                                 dtype, parts, stream) into a HIP graph once
                                 and replay it afterwards; calls on the null
                                 stream and profiled calls run eagerly       */
+    MLFMA_ONE_STREAM = 8     /* run every kernel on the caller's stream (by
+                                default the near field and the M2L of each
+                                level run on two library streams, forked
+                                from and joined back to the caller's stream
+                                with events, so they overlap the M2M chain) */
 };
 
 typedef struct mlfma_tree_info {

@@ -78,6 +78,11 @@ struct mlfma_ops_s {
     uint64_t pos_version = 0;
     std::vector<void *> allocs;
     int64_t last_R = 0;
+    // library streams for the concurrent schedule (near field; M2L) and
+    // the events that fork and join them
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_near = nullptr, ev_m2l = nullptr;
+    std::vector<hipEvent_t> ev_S;  // per level: multipoles ready
     // captured graphs of previous calls (MLFMA_USE_GRAPH)
     struct GraphEntry {
         const void *q = nullptr;
@@ -185,6 +190,19 @@ void free_ops(mlfma_ops_s *o)
     if (!o) return;
     prof_release(o);
     free_graphs(o);
+    {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess) {
+            (void)hipSetDevice(o->device);
+            for (hipStream_t &st : o->side)
+                if (st) (void)hipStreamDestroy(st);
+            for (hipEvent_t e : {o->ev_fork, o->ev_near, o->ev_m2l})
+                if (e) (void)hipEventDestroy(e);
+            for (hipEvent_t e : o->ev_S)
+                if (e) (void)hipEventDestroy(e);
+            (void)hipSetDevice(cur);
+        }
+    }
     if (!o->allocs.empty()) {
         int cur = 0;
         if (hipGetDevice(&cur) == hipSuccess) {
@@ -363,29 +381,45 @@ int autotune(mlfma_ops_s *o)
 }
 
 // The far field: C2M, M2M up the tree, M2L per level, L2L down the tree.
-// Leaves the leaf-level local expansions in lev[n_lev].Lloc.
-int run_far(mlfma_ops_s *o, int R, hipStream_t s)
+// Leaves the leaf-level local expansions in lev[n_lev].Lloc.  With `conc`
+// the M2L of a level runs on library stream side[1] as soon as the level's
+// multipoles are ready (event), overlapping the rest of the M2M chain; the
+// L2L chain waits for the last M2L.
+int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc)
 {
     const int nl = o->n_lev;
     DevLevel &leaf = o->lev[nl];
     const float kw = (float)o->k;
     const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
+    hipStream_t sm = conc ? o->side[1] : s;
+    auto m2l_level = [&](int l) -> int {
+        if (conc) {
+            CK(hipEventRecord(o->ev_S[l], s));
+            CK(hipStreamWaitEvent(sm, o->ev_S[l], 0));
+        }
+        hipStream_t s = sm;
+        DevLevel &D = o->lev[l];
+        LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s));
+        return MLFMA_OK;
+    };
     LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
+    if (int r = m2l_level(nl)) return r;
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
         if (P.interp_variant == 1) {
             LAUNCH(MLFMA_K_INTERP, launch_interp_onepass(o, l, R, s));
-            continue;
+        } else {
+            LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s, b3));
+            LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s, b3));
+            LAUNCH(MLFMA_K_INTERP_S3, dev::interp_s3(P.nbox, R, P.nth, P.nph, M, P.child_start, C.oct, o->X2, P.iG,
+                              P.shift, P.S, s));
         }
-        LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s, b3));
-        LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s, b3));
-        LAUNCH(MLFMA_K_INTERP_S3, dev::interp_s3(P.nbox, R, P.nth, P.nph, M, P.child_start, C.oct, o->X2, P.iG,
-                          P.shift, P.S, s));
+        if (int r = m2l_level(l)) return r;
     }
-    for (int l = 3; l <= nl; ++l) {
-        DevLevel &D = o->lev[l];
-        LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s));
+    if (conc) {
+        CK(hipEventRecord(o->ev_m2l, sm));
+        CK(hipStreamWaitEvent(s, o->ev_m2l, 0));
     }
     for (int l = 3; l < nl; ++l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
@@ -432,17 +466,30 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
         const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
         LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, cin, o->qs, s));
         const int64_t nnear = o->n * R * (field ? 3 : 1);
-        if (parts & MLFMA_NEAR)
-            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->n_p2p_heavy, o->pts, o->pt_start,
-                                         o->near_start, o->near_idx, o->leaf_coord,
-                                         (float)o->tree->leaf, (float)o->k, o->qs, R, field,
-                                         o->near, s));
-        else
-            LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
+        // concurrent schedule: the near field on side[0], forked after the
+        // gather and joined before L2O
+        const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM);
+        if (conc) {
+            CK(hipEventRecord(o->ev_fork, s));
+            CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
+        }
+        {
+            hipStream_t s0 = s;
+            hipStream_t s = conc ? o->side[0] : s0;
+            if (parts & MLFMA_NEAR)
+                LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->n_p2p_heavy, o->pts,
+                                             o->pt_start, o->near_start, o->near_idx,
+                                             o->leaf_coord, (float)o->tree->leaf, (float)o->k,
+                                             o->qs, R, field, o->near, s));
+            else
+                LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
+            if (conc) CK(hipEventRecord(o->ev_near, s));
+        }
         if (far) {
-            int r2 = run_far(o, R, s);
+            int r2 = run_far(o, R, s, conc);
             if (r2) return r2;
         }
+        if (conc) CK(hipStreamWaitEvent(s, o->ev_near, 0));
         DevLevel &leaf = o->lev[o->n_lev];
         if (far && !field && R >= 8) {
             // many right-hand sides: per-leaf product on the matrix cores
@@ -543,7 +590,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     if (digits < 1 || digits > 10) return fail(MLFMA_EINVAL, "precompute: digits outside 1..10");
     if (max_rhs < 1 || max_rhs > 1024)
         return fail(MLFMA_EINVAL, "precompute: max_rhs outside 1..1024");
-    if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE | MLFMA_USE_GRAPH))
+    if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE | MLFMA_USE_GRAPH |
+                            MLFMA_ONE_STREAM))
         return fail(MLFMA_EINVAL, "precompute: unknown flags");
     if (t->n_lev >= 3 && k * std::sqrt(3.0) * t->leaf < 1.0)
         return fail(MLFMA_EINVAL,
@@ -776,6 +824,19 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         }
         if (!(flags & MLFMA_NO_AUTOTUNE)) {
             if ((r = autotune(o))) return r;
+        }
+        // streams and events of the concurrent schedule (default priority)
+        if (!(flags & MLFMA_ONE_STREAM) && nl >= 3) {
+            for (hipStream_t &st : o->side)
+                if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+                    return fail(MLFMA_EDEVICE, "precompute: stream creation failed");
+            o->ev_S.assign(nl + 1, nullptr);
+            for (hipEvent_t *e : {&o->ev_fork, &o->ev_near, &o->ev_m2l})
+                if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+                    return fail(MLFMA_EDEVICE, "precompute: event creation failed");
+            for (int l = 3; l <= nl; ++l)
+                if (hipEventCreateWithFlags(&o->ev_S[l], hipEventDisableTiming) != hipSuccess)
+                    return fail(MLFMA_EDEVICE, "precompute: event creation failed");
         }
         return MLFMA_OK;
     }();

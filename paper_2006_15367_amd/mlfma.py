@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libmlfma.so")
 OK, EINVAL, EDEPTH, ENOMEM, EDEVICE, ERANGE = range(6)
 C64, C128 = 0, 1
 NEAR, FAR, CONJ = 1, 2, 4
-FP32, BF16X3_INTERP, NO_AUTOTUNE, USE_GRAPH = 0, 1, 2, 4
+FP32, BF16X3_INTERP, NO_AUTOTUNE, USE_GRAPH, ONE_STREAM = 0, 1, 2, 4, 8
 KERNELS = ["gather", "p2p", "c2m", "interp_s1", "interp_s2", "interp_s3", "m2l",
            "anterp_s1", "anterp_s2", "anterp_s3", "l2o", "interp", "anterp"]
 
@@ -229,11 +229,12 @@ class Operators:
     """Precomputed operators + device workspace (see
     mlfma_precompute_operators)."""
 
-    def __init__(self, tree, k, digits=3, max_rhs=1, bf16x3=False, autotune=True, graph=False):
+    def __init__(self, tree, k, digits=3, max_rhs=1, bf16x3=False, autotune=True, graph=False,
+                 one_stream=False):
         lib = _load()
         h = ctypes.c_void_p()
         flags = ((BF16X3_INTERP if bf16x3 else FP32) | (0 if autotune else NO_AUTOTUNE)
-                 | (USE_GRAPH if graph else 0))
+                 | (USE_GRAPH if graph else 0) | (ONE_STREAM if one_stream else 0))
         _check(lib.mlfma_precompute_operators(tree.handle, float(k), int(digits),
                                               int(max_rhs), flags, ctypes.byref(h)),
                "mlfma_precompute_operators")

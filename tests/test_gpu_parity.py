@@ -254,6 +254,34 @@ def test_batched_64_rhs_equals_single():
     assert e_d < 1e-3
 
 
+def test_concurrent_schedule_equals_one_stream(c1):
+    """The default schedule (near field and per-level M2L on library streams,
+    joined by events) gives the same numbers as every kernel on one stream:
+    the same kernels, each deterministic, with every dependency kept."""
+    torch = c1["torch"]
+    G = c1["G"]
+    say("c1: concurrent schedule vs one stream")
+    ops1 = G.Operators(c1["gt"], K, W.DIGITS, max_rhs=4, one_stream=True)
+    ops = c1["gops"]
+    # same variants on both handles
+    for k in ("m2l", "interp", "anterp"):
+        v = ops.variants(k)
+        for l in range(3, c1["ot"].n_lev + 1):
+            if v[l - 1] >= 0:
+                ops1.set_variant(l, v[l - 1], kernel=k)
+    rng = np.random.default_rng(77)
+    n = c1["xyz"].shape[0]
+    Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
+    Qd = torch.from_numpy(Q).cuda()
+    for rep in range(3):
+        a = _run(c1, ops.matvec, Qd)
+        b = _run(c1, ops1.matvec, Qd)
+        assert np.array_equal(a, b), rep
+    fa = _run(c1, ops.field, Qd[:, 0].contiguous())
+    fb = _run(c1, ops1.field, Qd[:, 0].contiguous())
+    assert np.array_equal(fa, fb)
+
+
 def test_graph_replays_match_eager(c1):
     """Captured graph of the whole matvec, replayed several times with eager
     work and synchronisations in between; every replay equals the eager
