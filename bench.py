@@ -232,8 +232,9 @@ def main():
         for _ in range(args.warmup):
             phi = ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
-        # one profiled (eager) step picks the dominant kernel
-        ops.profile_begin(None, 4096)
+        # one profiled (eager) step, every kernel timed alone, picks the
+        # dominant kernel
+        ops.profile_begin(None, 4096, serial=True)
         ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
         per_kernel = ops.profile_end()
@@ -261,6 +262,13 @@ def main():
             eager_ms = (time.perf_counter() - te0) * 1e3 / args.steps
         dom = ops.profile_end()[dominant]
         ms_per_step = (te - ts) * 1e3 / args.steps
+        # the same kernel timed alone: K more steps with every kernel on one
+        # stream (in the timed steps it shares the device with concurrent work)
+        ops.profile_begin([dominant], launches * args.steps + 16, serial=True)
+        for _ in range(args.steps):
+            ops.matvec(qd, stream=st)
+        torch.cuda.synchronize()
+        dom_alone = ops.profile_end()[dominant]
 
         # adjoint, timed the same way (no events)
         for _ in range(2):
@@ -274,6 +282,8 @@ def main():
 
     work = algorithmic_work(tinfo, levels, R, ops.variants("interp"), ops.variants("anterp"))
     rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
+    alone = roofline(dominant, work[dominant], dom_alone[0] / args.steps, launches, args.bf16x3)
+    rl["alone"] = {k: alone[k] for k in ("achieved", "frac", "avg_launch_us", "ms_per_step")}
     rl["traffic"] = recorded_traffic(dominant, args.workload, R)
     if rl["traffic"] is not None:
         rl["algorithmic_bytes_per_launch"] = round(work[dominant]["bytes"] / max(1, launches), 1)

@@ -282,8 +282,13 @@ enum mlfma_kernel_id {
  * bracketed by an event pair, for at most max_launches launches (the events
  * are created here).  mlfma_profile_end waits for the events, writes the
  * summed milliseconds and launch counts per id into ms[MLFMA_K_COUNT] and
- * launches[MLFMA_K_COUNT], and stops recording.
+ * launches[MLFMA_K_COUNT], and stops recording.  With MLFMA_PROFILE_SERIAL
+ * set in kernel_mask, calls made while recording run every kernel on the
+ * caller's stream (as MLFMA_ONE_STREAM does), so that each event pair times
+ * its kernel alone rather than while it shares the device with the near
+ * field or another level's M2L.
  */
+#define MLFMA_PROFILE_SERIAL 0x80000000u
 int mlfma_profile_begin(mlfma_ops_t ops, uint32_t kernel_mask,
                         int64_t max_launches);
 int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
@@ -293,7 +298,8 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * (out[l-1] for levels 1..n_levels; -1 where a level has no such kernel).
  * kernel = MLFMA_K_M2L: 0 per-observer lists from L2, 1 operators staged in
  * LDS, 2 sibling groups, 3 sibling groups with per-source records, 4 the
- * same with a slice-major sweep (for many right-hand sides).
+ * same with a slice-major sweep (for many right-hand sides), 5 the same with
+ * parent ranges balanced by record count and parents handed out dynamically.
  * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
  * and l+1, -1 on the leaf level and above level 3): 0 three passes through
  * HBM (ids _S1.._S3), 1 one pass with the intermediates in LDS.

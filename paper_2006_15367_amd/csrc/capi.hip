@@ -263,8 +263,10 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s)
                            D.base, D.typemap, D.T, D.S, R, D.Lloc, s);
     case 3:
     case 4:
+    case 5:
         return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
-                            D.rec_off, D.T, D.S, R, D.Lloc, s, variant == 4);
+                            D.rec_off, D.T, D.S, R, D.Lloc, s,
+                            variant == 3 ? 0 : variant == 4 ? 1 : 2);
     default:
         return dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s);
     }
@@ -346,7 +348,7 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < 5; ++v) {
+        for (int v = 0; v < 6; ++v) {
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -468,7 +470,8 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
         const int64_t nnear = o->n * R * (field ? 3 : 1);
         // concurrent schedule: the near field on side[0], forked after the
         // gather and joined before L2O
-        const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM);
+        const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM) &&
+                          !(o->prof_mask & MLFMA_PROFILE_SERIAL);
         if (conc) {
             CK(hipEventRecord(o->ev_fork, s));
             CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
@@ -776,7 +779,20 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                                                                : (int32_t)ty[i] * 64 * (int32_t)sizeof(float2));
                         }
                     }
+                    // pad the parent's records to a multiple of 4 with records
+                    // that add zero (the last source again, every slot on the
+                    // zero row), so the kernel walks them in whole batches
+                    while ((rsrc.size() - (size_t)rs[p]) % 4 != 0) {
+                        rsrc.push_back(rsrc.back());
+                        for (int i = 0; i < 8; ++i) roff.push_back(zero_row);
+                    }
                     rs[p + 1] = (int32_t)rsrc.size();
+                }
+                // 8 zero records after the last list: the kernel's pipeline
+                // fetches up to two batches of 4 past the end of a list
+                for (int u = 0; u < 8; ++u) {
+                    rsrc.push_back(0);
+                    for (int i = 0; i < 8; ++i) roff.push_back(zero_row);
                 }
                 if ((r = upload(o, &D.rec_start, rs.data(), (int64_t)rs.size()))) return r;
                 if ((r = upload(o, &D.rec_src, rsrc.data(), (int64_t)rsrc.size()))) return r;
@@ -1021,7 +1037,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-        if (variant < 0 || variant > 4) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant < 0 || variant > 5) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         o->lev[level].m2l_variant = variant;
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)

@@ -85,12 +85,17 @@ hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start,
 
 // M2L by sibling groups with per-source records: rec_src[e] source box,
 // rec_off[8e + i] byte offset of the operator row of (child i of the parent,
-// source) in the LDS slice of 64 samples (row ntypes = zeros: no interaction)
-// (sweep: the slice-major schedule for many right-hand sides)
+// source) in the LDS slice of 64 samples (row ntypes = zeros: no interaction);
+// each parent's records are padded to a multiple of 4 with zero records
+// compute units of the current device
+int cu_count();
+
+// schedule: 0 contiguous parent ranges, 1 the slice-major sweep for many
+// right-hand sides, 2 ranges balanced by record count with dynamic parents
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
-                   bool sweep);
+                   int schedule);
 
 // M2L per observer with the operator slice in LDS
 hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start,

@@ -13,6 +13,21 @@
 namespace mlfma {
 namespace dev {
 
+// Compute units of the current device (cached per device).
+int cu_count()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
 // ------------------------------------------------------------------- M2L --
 // Copy T[t][k0 .. k0+KC) (zero beyond K) for all t < ntypes into Ts[t][KC]
 // with 8 loads in flight per thread before the LDS stores.
@@ -323,49 +338,114 @@ hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start
 // load of the source spectrum and, per sibling, one LDS read and four FMAs:
 // no per-pair branches, no per-pair scalar arithmetic.  The operators of
 // the level for the 64 samples sit in LDS ((316 + 1) x 64 x 8 B <= 160 KB).
+// The records of a parent are walked in batches of U (the host pads every
+// list to a multiple of 4 and appends 8 zero records after the last list).
+// The spectra of source s for right-hand side c sit at S + s * sstride +
+// voff[c] (32-bit lane offsets).
+//
+// One right-hand side: a three-stage software pipeline.  The record data
+// and the source spectra of batches j+1 and j+2 are requested before batch
+// j is computed, so a wave has three batches of loads in flight; the two
+// batches past the end of the list are fetched and never used (they read
+// the next list or the appended records).  The spectra are read through a buffer resource based
+// at the source (scalar address arithmetic only).
+template <int NO>
+__device__ __forceinline__ void m2l_rec_parent1(const char *Tsb, int lane8, int e0, int e1,
+                                                const int32_t *__restrict__ rec_src,
+                                                const int32_t *__restrict__ rec_off,
+                                                const char *__restrict__ Sb, uint64_t sstride,
+                                                uint32_t voff, float2 (&acc)[8][1])
+{
+    constexpr int U = NO > 4 ? 2 : 4;  // records per batch
+    const int nb = (e1 - e0) / U;
+    if (nb <= 0) return;
+    const int32_t *rs = rec_src + e0;
+    const int32_t *ro = rec_off + 8 * (int64_t)e0;
+    float2 va[U], vb[U], vc[U];
+    int oa[U][NO], ob[U][NO], oc[U][NO];
+    auto fetch = [&](int j, float2 (&v)[U], int (&of)[U][NO]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int sidx = rs[j * U + u];
+#pragma unroll
+            for (int i = 0; i < NO; ++i) of[u][i] = ro[8 * (j * U + u) + i];
+            const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(Sb + (uint64_t)(uint32_t)sidx * sstride), (short)0, (int)sstride,
+                0x00020000);
+            // two 32-bit loads: this compiler lowers the 64-bit buffer-load
+            // builtin to a 32-bit load
+            const uint32_t re = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, 0, 0);
+            const uint32_t im = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff + 4, 0, 0);
+            v[u] = make_float2(__builtin_bit_cast(float, re), __builtin_bit_cast(float, im));
+        }
+    };
+    auto compute = [&](const float2 (&v)[U], const int (&of)[U][NO]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                const float2 tv = *(const float2 *)(Tsb + (of[u][i] + lane8));
+                acc[i][0] = cfma(tv, v[u], acc[i][0]);
+            }
+    };
+    fetch(0, va, oa);
+    fetch(1, vb, ob);
+    for (int j = 0;;) {
+        fetch(j + 2, vc, oc);
+        compute(va, oa);
+        if (++j >= nb) break;
+        fetch(j + 2, va, oa);
+        compute(vb, ob);
+        if (++j >= nb) break;
+        fetch(j + 2, vb, ob);
+        compute(vc, oc);
+        if (++j >= nb) break;
+    }
+}
+
+// Several right-hand sides: batches of U records, the scalar record data of
+// the next batch loaded while the current one computes (one scalar-load
+// latency per batch); the spectrum loads of a batch are shared by RC
+// right-hand sides.  (The two-stage pipeline of the one-RHS loop measured
+// slower here: 7.1 against 6.0 ms at 64 right-hand sides on the 262k sphere.)
 template <int RC, int NO>
 __device__ __forceinline__ void m2l_rec_parent(const char *Tsb, int lane8, int e0, int e1,
                                                const int32_t *__restrict__ rec_src,
                                                const int32_t *__restrict__ rec_off,
-                                               const float2 *__restrict__ S, int64_t K, int R,
-                                               int r0, int rc, int64_t kk, float2 (&acc)[8][RC])
+                                               const char *__restrict__ Sb, uint64_t sstride,
+                                               const uint32_t (&voff)[RC], float2 (&acc)[8][RC])
 {
-    constexpr int U = RC >= 8 ? 2 : 4;  // records in flight per wave
-    // the scalar record data of the next U records is loaded while the
-    // current ones compute (one scalar-load latency per U records)
+    constexpr int U = 4;
     int src[U], off[U][NO];
     auto load_rec = [&](int eb, int (&sr)[U], int (&of)[U][NO]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = eb + u < e1 ? eb + u : e1 - 1;
-            sr[u] = rec_src[e];
+            sr[u] = rec_src[eb + u];
 #pragma unroll
-            for (int i = 0; i < NO; ++i) of[u][i] = rec_off[8 * e + i];
+            for (int i = 0; i < NO; ++i) of[u][i] = rec_off[8 * (eb + u) + i];
         }
     };
+    if (e1 <= e0) return;
     load_rec(e0, src, off);
     for (int eb = e0; eb < e1; eb += U) {
         float2 sv[U][RC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const float2 *Sr = S + ((int64_t)src[u] * R + r0) * K + kk;
+            const char *base = Sb + (uint64_t)(uint32_t)src[u] * sstride;
 #pragma unroll
-            for (int c = 0; c < RC; ++c)
-                sv[u][c] = (RC == 1 || c < rc) ? Sr[c * K] : make_float2(0.f, 0.f);
+            for (int c = 0; c < RC; ++c) sv[u][c] = *(const float2 *)(base + voff[c]);
         }
+        // the batch after the last reads the next list or the appended records
         int nsrc[U], noff[U][NO];
-        load_rec(eb + U < e1 ? eb + U : eb, nsrc, noff);
+        load_rec(eb + U, nsrc, noff);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (eb + u < e1) {
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int i = 0; i < NO; ++i) {
-                    const float2 tv = *(const float2 *)(Tsb + (off[u][i] + lane8));
+            for (int i = 0; i < NO; ++i) {
+                const float2 tv = *(const float2 *)(Tsb + (off[u][i] + lane8));
 #pragma unroll
-                    for (int c = 0; c < RC; ++c) acc[i][c] = cfma(tv, sv[u][c], acc[i][c]);
-                }
+                for (int c = 0; c < RC; ++c) acc[i][c] = cfma(tv, sv[u][c], acc[i][c]);
             }
-        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             src[u] = nsrc[u];
@@ -380,15 +460,19 @@ __global__ void __launch_bounds__(64 * NW)
 k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ child_start,
           const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
           const int32_t *__restrict__ rec_off, const float2 *__restrict__ T,
-          const float2 *__restrict__ S, int R, int nkc, int64_t ppb, int nwg,
+          const float2 *__restrict__ S, int R, int nkc, int nrange, int nwg, int balanced,
           float2 *__restrict__ Lout)
 {
     // Two schedules (about one workgroup per CU either way, so the LDS
     // staging of the operators is amortised over many parents):
     //  nwg == 0: workgroup w serves sample chunk w % nkc, right-hand-side
-    //    chunk blockIdx.z and the contiguous parent range (w / nkc) * ppb
-    //    ... + ppb; its NW waves take those parents round-robin.  (Numbering
-    //    the workgroups so that each XCD gets a contiguous run of ranges
+    //    chunk blockIdx.z and parent range w / nkc of nrange contiguous
+    //    ranges.  balanced == 0: ranges of equal parent counts, taken by the
+    //    NW waves round-robin.  balanced == 1: ranges holding equal numbers
+    //    of records (bounds found by binary search in the record offsets),
+    //    the waves taking parents one at a time from a counter in LDS, so a
+    //    wave that drew short lists takes more of them.  (Numbering the
+    //    workgroups so that each XCD gets a contiguous run of ranges
     //    measured slower at one RHS.)
     //  nwg > 0: slice-major sweep for many right-hand sides.  The nwg
     //    workgroups of one (sample chunk, RHS chunk) slice are consecutive,
@@ -397,13 +481,18 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
     //    stay within one window of the Morton order, small enough for the
     //    Infinity Cache, instead of every slice streaming at once.
     extern __shared__ float2 Ts[];  // [ntypes + 1][64], row ntypes = 0
-    const int64_t w = nwg ? blockIdx.x % nwg : blockIdx.x;
+    __shared__ int next_parent;
+    // balanced: workgroups renumbered so that each XCD (they are dealt to
+    // the 8 XCDs round-robin) serves a contiguous run of ranges
+    const int64_t w = nwg ? blockIdx.x % nwg
+                          : (balanced ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x);
     const int64_t slice = nwg ? blockIdx.x / nwg : 0;
     const int kc = nwg ? (int)(slice % nkc) : (int)(w % nkc);
     const int64_t k0 = (int64_t)kc * 64;
     stage_t_slice<64>(Ts, T, ntypes, K, k0);
     for (int idx = threadIdx.x; idx < 64; idx += blockDim.x)
         Ts[ntypes * 64 + idx] = make_float2(0.f, 0.f);
+    if (threadIdx.x == 0) next_parent = 0;
     __syncthreads();
     const char *Tsb = (const char *)Ts;
     const int lane = threadIdx.x & 63;
@@ -413,11 +502,50 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
     const int64_t kk = valid ? k : K - 1;
     const int r0 = (nwg ? (int)(slice / nkc) : (int)blockIdx.z) * RC;
     const int rc = min(RC, R - r0);
-    const int64_t pbeg = nwg ? w * NW : (w / nkc) * ppb;
-    const int64_t pend = nwg ? nparent : min(nparent, pbeg + ppb);
-    const int64_t pstep = nwg ? (int64_t)nwg * NW : NW;
+    // lane offsets of the right-hand sides (a missing one re-reads r0)
+    const uint64_t sstride = (uint64_t)R * (uint64_t)K * sizeof(float2);
+    uint32_t voff[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+        // (a multiple of 8 below 2^31: the mask states it, so the two
+        // 32-bit loads of a value merge into one 64-bit load)
+        voff[c] = (uint32_t)(((int64_t)(r0 + (c < rc ? c : 0)) * K + kk) * (int64_t)sizeof(float2)) &
+                  0x7ffffff8u;
+    const char *Sb = (const char *)S;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t P = pbeg + wave; P < pend; P += pstep) {
+    int64_t pbeg, pend;
+    if (nwg) {
+        pbeg = w * NW + wave;
+        pend = nparent;
+    } else if (!balanced) {
+        const int64_t ppb = (nparent + nrange - 1) / nrange;
+        pbeg = (w / nkc) * ppb;
+        pend = min(nparent, pbeg + ppb);
+    } else {
+        // first parent whose records start at or after the target
+        const int64_t total = rec_start[nparent];
+        const int64_t rg = w / nkc;
+        auto lower = [&](int64_t target) -> int64_t {
+            int64_t lo = 0, hi = nparent;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)__builtin_amdgcn_readfirstlane(rec_start[mid]) < target) lo = mid + 1;
+                else hi = mid;
+            }
+            return lo;
+        };
+        pbeg = rg == 0 ? 0 : lower(total * rg / nrange);
+        pend = rg == nrange - 1 ? nparent : lower(total * (rg + 1) / nrange);
+    }
+    // the next parent of this wave: interleaved (sweep) or from the counter
+    auto take = [&](int64_t prev) -> int64_t {
+        if (nwg) return prev + (int64_t)nwg * NW;
+        if (!balanced) return prev + NW;
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&next_parent, 1);
+        return pbeg + __builtin_amdgcn_readfirstlane(t);
+    };
+    for (int64_t P = nwg ? pbeg : (balanced ? take(0) : pbeg + wave); P < pend; P = take(P)) {
         const int o0 = __builtin_amdgcn_readfirstlane(child_start[P]);
         const int no = __builtin_amdgcn_readfirstlane(child_start[P + 1]) - o0;
         const int e0 = __builtin_amdgcn_readfirstlane(rec_start[P]);
@@ -430,7 +558,10 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
         switch (no) {
 #define REC_CASE(N)                                                                          \
     case N:                                                                                  \
-        m2l_rec_parent<RC, N>(Tsb, lane8, e0, e1, rec_src, rec_off, S, K, R, r0, rc, kk, acc); \
+        if constexpr (RC == 1)                                                               \
+            m2l_rec_parent1<N>(Tsb, lane8, e0, e1, rec_src, rec_off, Sb, sstride, voff[0], acc); \
+        else                                                                                 \
+            m2l_rec_parent<RC, N>(Tsb, lane8, e0, e1, rec_src, rec_off, Sb, sstride, voff, acc); \
         break;
             REC_CASE(1) REC_CASE(2) REC_CASE(3) REC_CASE(4)
             REC_CASE(5) REC_CASE(6) REC_CASE(7) REC_CASE(8)
@@ -451,35 +582,43 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
-                   bool sweep)
+                   int schedule)
 {
+    const bool sweep = schedule == 1;
     if (nparent == 0 || K == 0) return hipSuccess;
     const size_t lds = (size_t)(ntypes + 1) * 64 * sizeof(float2);
-    if (lds > 163840) return hipErrorInvalidValue;
+    if (lds + 16 > 163840) return hipErrorInvalidValue;  // + the static counter
+    // 32-bit lane offsets (and buffer range) within one source's spectra
+    if ((uint64_t)R * (uint64_t)K * sizeof(float2) > 0x7fffffffull) return hipErrorInvalidValue;
     // right-hand sides per thread: 1 or 4 (8 per thread, with 8 waves per
     // workgroup for the registers of 8 x 8 accumulators, measured slower at
     // 64 right-hand sides: 10.1 ms against 8.3 ms on the 262k sphere)
     const int RC = R == 1 ? 1 : 4;
     const int NW = 16;
     const int nkc = (int)((K + 63) / 64);
+    // the LDS slice allows one workgroup per CU: size the grid to the CU
+    // count, as one workgroup more than the CUs doubles the kernel's time
+    const int ncu = cu_count();
     const int nz = (R + RC - 1) / RC;
     dim3 grid;
-    int64_t ppb = 0;
+    int nrange = 0;
     int nwg = 0;
     if (sweep) {
         // one workgroup per CU per slice, slices one after the other
-        nwg = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nparent + NW - 1) / NW));
+        nwg = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, (nparent + NW - 1) / NW));
         grid = dim3((unsigned)(nwg * nkc * nz), 1, 1);
     } else {
-        // about one workgroup per CU in all, at least one parent per wave
-        const int64_t per = std::max<int64_t>(
-            1, std::min<int64_t>((256 + nkc * nz - 1) / (nkc * nz), (nparent + NW - 1) / NW));
-        ppb = (nparent + per - 1) / per;
-        grid = dim3((unsigned)(nkc * ((nparent + ppb - 1) / ppb)), 1, (unsigned)nz);
+        // at most one workgroup per CU in all, at least one parent per wave
+        nrange = (int)std::max<int64_t>(
+            1, std::min<int64_t>(ncu / (nkc * nz), (nparent + NW - 1) / NW));
+        if (schedule == 0) nrange = (int)((nparent + (nparent + nrange - 1) / nrange - 1) /
+                                          ((nparent + nrange - 1) / nrange));
+        grid = dim3((unsigned)(nkc * nrange), 1, (unsigned)nz);
     }
 #define M2L_REC(RCV, NWV)                                                                      \
     hipLaunchKernelGGL((k_m2l_rec<RCV, NWV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
-                       child_start, rec_start, rec_src, rec_off, T, S, R, nkc, ppb, nwg, Lout)
+                       child_start, rec_start, rec_src, rec_off, T, S, R, nkc, nrange, nwg,   \
+                       schedule == 2 ? 1 : 0, Lout)
     if (RC == 1) M2L_REC(1, 16);
     else M2L_REC(4, 16);
 #undef M2L_REC

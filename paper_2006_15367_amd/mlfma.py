@@ -17,6 +17,7 @@ OK, EINVAL, EDEPTH, ENOMEM, EDEVICE, ERANGE = range(6)
 C64, C128 = 0, 1
 NEAR, FAR, CONJ = 1, 2, 4
 FP32, BF16X3_INTERP, NO_AUTOTUNE, USE_GRAPH, ONE_STREAM = 0, 1, 2, 4, 8
+PROFILE_SERIAL = 0x80000000
 KERNELS = ["gather", "p2p", "c2m", "interp_s1", "interp_s2", "interp_s3", "m2l",
            "anterp_s1", "anterp_s2", "anterp_s3", "l2o", "interp", "anterp"]
 
@@ -325,10 +326,12 @@ class Operators:
         _check(_load().mlfma_ops_set_variant(self._h, KERNELS.index(kernel), int(level),
                                              int(variant)), "mlfma_ops_set_variant")
 
-    def profile_begin(self, kernels=None, max_launches=4096):
-        """Start HIP-event timing of the named kernels (default: all)."""
+    def profile_begin(self, kernels=None, max_launches=4096, serial=False):
+        """Start HIP-event timing of the named kernels (default: all).  With
+        serial=True the timed calls run every kernel on the caller's stream,
+        so each kernel is timed alone."""
         names = KERNELS if kernels is None else kernels
-        mask = 0
+        mask = PROFILE_SERIAL if serial else 0
         for nme in names:
             mask |= 1 << KERNELS.index(nme)
         _check(_load().mlfma_profile_begin(self._h, mask, int(max_launches)),
