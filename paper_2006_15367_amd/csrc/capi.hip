@@ -250,7 +250,8 @@ int refresh_positions(mlfma_ops_s *o)
 }
 
 // ---------------------------------------------------------------- matvec --
-hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s)
+// max_wg: workgroup cap of the record variants (0: one per CU)
+hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, int max_wg = 0)
 {
     DevLevel &D = o->lev[l];
     DevLevel &Pl = o->lev[l - 1];
@@ -266,7 +267,7 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s)
     case 5:
         return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
                             D.rec_off, D.T, D.S, R, D.Lloc, s,
-                            variant == 3 ? 0 : variant == 4 ? 1 : 2);
+                            variant == 3 ? 0 : variant == 4 ? 1 : 2, max_wg);
     default:
         return dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s);
     }
@@ -387,7 +388,8 @@ int autotune(mlfma_ops_s *o)
 // the M2L of a level runs on library stream side[1] as soon as the level's
 // multipoles are ready (event), overlapping the rest of the M2M chain; the
 // L2L chain waits for the last M2L.
-int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc)
+template <class Near>
+int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
 {
     const int nl = o->n_lev;
     DevLevel &leaf = o->lev[nl];
@@ -401,7 +403,11 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc)
         }
         hipStream_t s = sm;
         DevLevel &D = o->lev[l];
-        LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s));
+        // concurrent: the record variants leave a quarter of the CUs (their
+        // workgroups hold a CU's whole LDS) to the upward chain, the
+        // critical path, which otherwise waits for M2L workgroups to retire
+        const int cap = conc ? dev::cu_count() - dev::cu_count() / 4 : 0;
+        LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s, cap));
         return MLFMA_OK;
     };
     LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
@@ -419,6 +425,11 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc)
         }
         if (int r = m2l_level(l)) return r;
     }
+    // the near field joins here: it fills the device during the downward
+    // pass, whose small kernels leave most CUs idle (forked at the start,
+    // it took CUs from C2M and the upward chain)
+    if (conc)
+        if (int r = near()) return r;
     if (conc) {
         CK(hipEventRecord(o->ev_m2l, sm));
         CK(hipStreamWaitEvent(s, o->ev_m2l, 0));
@@ -472,11 +483,11 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
         // gather and joined before L2O
         const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM) &&
                           !(o->prof_mask & MLFMA_PROFILE_SERIAL);
-        if (conc) {
-            CK(hipEventRecord(o->ev_fork, s));
-            CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
-        }
-        {
+        auto near = [&]() -> int {
+            if (conc) {
+                CK(hipEventRecord(o->ev_fork, s));
+                CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
+            }
             hipStream_t s0 = s;
             hipStream_t s = conc ? o->side[0] : s0;
             if (parts & MLFMA_NEAR)
@@ -487,9 +498,13 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
             else
                 LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
             if (conc) CK(hipEventRecord(o->ev_near, s));
-        }
+            return MLFMA_OK;
+        };
+        // one stream: the near field first; concurrent: from the far pass
+        if (!conc)
+            if (int r = near()) return r;
         if (far) {
-            int r2 = run_far(o, R, s, conc);
+            int r2 = run_far(o, R, s, conc, near);
             if (r2) return r2;
         }
         if (conc) CK(hipStreamWaitEvent(s, o->ev_near, 0));

@@ -604,10 +604,14 @@ static hipError_t launch_rowgemm(const P &p, hipStream_t s, int gridy = 1, int c
 
 // M2M s3: one wave per (parent p, rhs r, block of 8 theta' rows, chunk of
 // 16*NT phi' columns); the 4 waves of a workgroup share the column chunk,
-// whose slice of the synthesis matrix G is staged in LDS.  The wave loops
-// over the children, multiplies each child's block by its shift and
-// accumulates the parent in registers.
-template <int NT>
+// whose slice of the synthesis matrix G (zero rows past M) is staged in
+// LDS.  The wave walks its children in steps of 4*MKB orders: the lane
+// loads all MKB of its A values of a step (one float each: the real or the
+// imaginary part of the child's row) one step ahead, so the loads of the
+// next step (possibly the next child's) are in flight during the MFMAs of
+// this one; a child's shift values are requested at its first step and
+// applied after its last, accumulating the parent in registers.
+template <int NT, int MKB>
 __global__ void __launch_bounds__(256)
 k_m2m_s3(const float2 *__restrict__ T2, const float *__restrict__ G,
          const float2 *__restrict__ shift, const int32_t *__restrict__ child_start,
@@ -616,25 +620,28 @@ k_m2m_s3(const float2 *__restrict__ T2, const float *__restrict__ G,
 {
     extern __shared__ float Gs[];
     constexpr int NC = 16 * NT;
+    constexpr int KS = 4 * MKB;  // orders per step
     const int lane = threadIdx.x & 63;
     const int nch = (nphp + NC - 1) / NC;
+    const int nkb = (M + KS - 1) / KS;  // steps per child
+    const int MP = nkb * KS;            // staged rows (zeros past M)
     const int64_t blk = xcd_contiguous_i(blockIdx.x, gridDim.x);
     const int chunk = (int)(blk % nch);
     const int n0 = chunk * NC;
     const int64_t wave = (blk / nch) * 4 + (threadIdx.x >> 6);
     const int ntb = (nthp + 7) / 8;
-    for (int base = threadIdx.x; base < M * NC; base += 8 * blockDim.x) {
+    for (int base = threadIdx.x; base < MP * NC; base += 8 * blockDim.x) {
         float v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int idx = base + u * blockDim.x;
             const int k = idx / NC, n = idx - (idx / NC) * NC;
-            v[u] = (idx < M * NC && n0 + n < nphp) ? G[k * nphp + n0 + n] : 0.f;
+            v[u] = (idx < MP * NC && k < M && n0 + n < nphp) ? G[k * nphp + n0 + n] : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int idx = base + u * blockDim.x;
-            if (idx < M * NC) Gs[idx] = v[u];
+            if (idx < MP * NC) Gs[idx] = v[u];
         }
     }
     __syncthreads();
@@ -648,41 +655,35 @@ k_m2m_s3(const float2 *__restrict__ T2, const float *__restrict__ G,
     const int th_a = tb * 8 + t;
     const bool rv = th_a < nthp;
     const int c0 = child_start[p], c1 = child_start[p + 1];
+    const int nsteps = (c1 - c0) * nkb;
     float2 par[NT][2];
 #pragma unroll
     for (int j = 0; j < NT; ++j) par[j][0] = par[j][1] = make_float2(0.f, 0.f);
-    for (int c = c0; c < c1; ++c) {
-        const float2 *A = T2 + ((int64_t)c * R + r) * M * nthp + th_a;  // A[k * nthp]
-        floatx4 acc[NT];
+    if (nsteps == 0) {
+        float2 *out = Sp + (p * R + r) * Kp;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-        int kb = 0;
-        for (; kb + 8 <= M; kb += 8) {
-            float av[2];
+        for (int j = 0; j < NT; ++j) {
+            const int n = n0 + 16 * j + (lane & 15);
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const float2 x = rv ? A[(int64_t)(kb + 4 * u + kq) * nthp] : make_float2(0.f, 0.f);
-                av[u] = part ? x.y : x.x;
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int j = 0; j < NT; ++j)
-                    acc[j] = mfma4(av[u], Gs[(kb + 4 * u + kq) * NC + 16 * j + (lane & 15)], acc[j]);
-        }
-        for (; kb < M; kb += 4) {
-            const int k = kb + kq;
-            float av = 0.f;
-            if (rv && k < M) {
-                const float2 x = A[(int64_t)k * nthp];
-                av = part ? x.y : x.x;
-            }
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const float bv = k < M ? Gs[k * NC + 16 * j + (lane & 15)] : 0.f;
-                acc[j] = mfma4(av, bv, acc[j]);
+            for (int h = 0; h < 2; ++h) {
+                const int th = tb * 8 + 2 * kq + h;
+                if (n < nphp && th < nthp) out[(int64_t)th * nphp + n] = par[j][h];
             }
         }
+        return;
+    }
+    auto load_step = [&](int st, float (&a)[MKB]) {
+        const int c = c0 + st / nkb;
+        const int kb0 = (st % nkb) * KS;
+        const float *A = (const float *)(T2 + ((int64_t)c * R + r) * M * nthp + th_a) + part;
+#pragma unroll
+        for (int u = 0; u < MKB; ++u) {
+            const int k = kb0 + 4 * u + kq;
+            a[u] = (rv && k < M) ? A[2 * (int64_t)k * nthp] : 0.f;
+        }
+    };
+    float2 sv[NT][2];
+    auto load_shift = [&](int c) {
         const float2 *sh = shift + (int64_t)child_oct[c] * Kp;
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
@@ -690,14 +691,46 @@ k_m2m_s3(const float2 *__restrict__ T2, const float *__restrict__ G,
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int th = tb * 8 + 2 * kq + h;
-                if (n < nphp && th < nthp) {
-                    const float2 sv = sh[(int64_t)th * nphp + n];
-                    const float yr = acc[j][2 * h], yi = acc[j][2 * h + 1];
-                    par[j][h].x += sv.x * yr - sv.y * yi;
-                    par[j][h].y += sv.x * yi + sv.y * yr;
-                }
+                sv[j][h] = (n < nphp && th < nthp) ? sh[(int64_t)th * nphp + n] : make_float2(0.f, 0.f);
             }
         }
+    };
+    floatx4 acc[NT];
+    auto compute = [&](int st, const float (&a)[MKB]) {
+        const int kb0 = (st % nkb) * KS;
+        if (kb0 == 0) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // narrow chunks: the shift values in flight during the MFMAs
+            // (wide ones load them after, to keep their registers free)
+            if constexpr (NT <= 2) load_shift(c0 + st / nkb);
+        }
+#pragma unroll
+        for (int u = 0; u < MKB; ++u)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[j] = mfma4(a[u], Gs[(kb0 + 4 * u + kq) * NC + 16 * j + (lane & 15)], acc[j]);
+        if (kb0 + KS >= M) {
+            if constexpr (NT > 2) load_shift(c0 + st / nkb);
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float yr = acc[j][2 * h], yi = acc[j][2 * h + 1];
+                    par[j][h].x += sv[j][h].x * yr - sv[j][h].y * yi;
+                    par[j][h].y += sv[j][h].x * yi + sv[j][h].y * yr;
+                }
+        }
+    };
+    float a0[MKB], a1[MKB];
+    load_step(0, a0);
+    for (int st = 0;;) {
+        if (st + 1 < nsteps) load_step(st + 1, a1);
+        compute(st, a0);
+        if (++st >= nsteps) break;
+        if (st + 1 < nsteps) load_step(st + 1, a0);
+        compute(st, a1);
+        if (++st >= nsteps) break;
     }
     float2 *out = Sp + (p * R + r) * Kp;
 #pragma unroll
@@ -754,20 +787,31 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M, const int3
     const int64_t waves = nboxp * R * ((nthp + 7) / 8);
     if (waves == 0) return hipSuccess;
     // widest column chunk that still gives >= 2048 waves (and fits 64 KB)
-    int nt = pick_nt(M, nphp);
+    // orders per step: one step per child up to 68 orders
+    const int mkb = M <= 20 ? 5 : M <= 28 ? 7 : M <= 44 ? 11 : 17;
+    const int mp = (M + 4 * mkb - 1) / (4 * mkb) * 4 * mkb;
+    int nt = pick_nt(mp, nphp);
     while (nt > 1 && waves * ((nphp + 16 * nt - 1) / (16 * nt)) < 2048) nt >>= 1;
     const int nch = (nphp + 16 * nt - 1) / (16 * nt);
     dim3 grid((unsigned)(waves_to_blocks(waves) * nch)), block(256);
-    const size_t lds = (size_t)M * 16 * nt * sizeof(float);
-#define M2M_S3(NTV)                                                                        \
-    hipLaunchKernelGGL((k_m2m_s3<NTV>), grid, block, lds, s, T2, G, shift, child_start,    \
+    const size_t lds = (size_t)mp * 16 * nt * sizeof(float);
+#define M2M_S3(NTV, MKBV)                                                                        \
+    hipLaunchKernelGGL((k_m2m_s3<NTV, MKBV>), grid, block, lds, s, T2, G, shift, child_start,    \
                        child_oct, Sp, nboxp, R, nthp, nphp, M)
-    switch (nt) {
-    case 1: M2M_S3(1); break;
-    case 2: M2M_S3(2); break;
-    case 4: M2M_S3(4); break;
-    default: M2M_S3(8); break;
+#define M2M_S3_NT(MKBV)                  \
+    switch (nt) {                        \
+    case 1: M2M_S3(1, MKBV); break;      \
+    case 2: M2M_S3(2, MKBV); break;      \
+    case 4: M2M_S3(4, MKBV); break;      \
+    default: M2M_S3(8, MKBV); break;     \
     }
+    switch (mkb) {
+    case 5: M2M_S3_NT(5); break;
+    case 7: M2M_S3_NT(7); break;
+    case 11: M2M_S3_NT(11); break;
+    default: M2M_S3_NT(17); break;
+    }
+#undef M2M_S3_NT
 #undef M2M_S3
     return hipGetLastError();
 }

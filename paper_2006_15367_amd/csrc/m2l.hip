@@ -582,7 +582,7 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
-                   int schedule)
+                   int schedule, int max_wg)
 {
     const bool sweep = schedule == 1;
     if (nparent == 0 || K == 0) return hipSuccess;
@@ -598,7 +598,7 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
     const int nkc = (int)((K + 63) / 64);
     // the LDS slice allows one workgroup per CU: size the grid to the CU
     // count, as one workgroup more than the CUs doubles the kernel's time
-    const int ncu = cu_count();
+    const int ncu = max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count();
     const int nz = (R + RC - 1) / RC;
     dim3 grid;
     int nrange = 0;
