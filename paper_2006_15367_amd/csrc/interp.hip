@@ -158,11 +158,18 @@ struct ProbS3L {
         const int th = (int)row - cr * nth;
         return T2[((int64_t)cr * K + k) * nth + th];
     }
+    // row (c, r, theta) decoded once; sample k of it sits k * nth further
     struct Row {
-        int64_t row;
+        const float2 *x;
+        int stride;
     };
-    __device__ Row row_at(int64_t row) const { return Row{row}; }
-    __device__ float2 at(const Row &w, int k) const { return a(w.row, k); }
+    __device__ Row row_at(int64_t row) const
+    {
+        const int cr = (int)row / nth;
+        const int th = (int)row - cr * nth;
+        return Row{T2 + (int64_t)cr * K * nth + th, nth};
+    }
+    __device__ float2 at(const Row &w, int k) const { return w.x[(int64_t)k * w.stride]; }
     __device__ float b(int k, int n) const { return G[k * N + n]; }
     __device__ void store(int64_t row, int n, float2 v) const
     {
@@ -290,27 +297,72 @@ __global__ void __launch_bounds__(256) k_s2(ProbS2 p)
 }
 
 // Same contraction with the data tile staged in LDS as well: a workgroup
-// loops over tiles of 32 complex rows (grid-stride), copies each tile with
-// coalesced loads into LDS, and its 4 waves read their MFMA fragments from
-// LDS.  The operator block is staged once per workgroup and column chunk.
-// Used when K <= 128.
-template <class P, int NT>
+// loops over tiles of 32 complex rows (grid-stride), copies each tile into
+// LDS, and its 4 waves read their MFMA fragments from LDS.  The operator
+// block is staged once per workgroup and column chunk (16*NT columns, NT =
+// 1..8).  The loads of the next tile go to registers (at most 16 values a
+// thread) before the MFMAs of the current one, so they are in flight while
+// it computes.  Used when K <= 128; QMAX >= (K rounded up to 4) / 8.
+template <class P, int NT, int QMAX>
 __global__ void __launch_bounds__(256) k_rowgemm_lds(P p, int col_override)
 {
     extern __shared__ float smem[];
     constexpr int NC = 16 * NT;
     const int K = p.K;
-    const int KP = ((K + 3) & ~3) + 1;        // row pitch in float2 (odd: spreads banks)
+    const int K4 = (K + 3) & ~3;
+    const int KP = K4 + 1;                    // row pitch in float2 (odd: spreads banks)
+    const int nq = (K4 + 7) / 8;              // values per thread per tile
     float *Bs = smem;                         // [K4][NC]
-    float2 *As = (float2 *)(smem + ((K + 3) & ~3) * NC);  // [32][KP]
+    float2 *As = (float2 *)(smem + K4 * NC);  // [32][KP]
     if (col_override >= 0) p.set_col(col_override + blockIdx.y);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int t = (lane & 15) >> 1, part = lane & 1, kq = lane >> 4;
     const int64_t ntiles = (p.nrows + 31) / 32;
-    const int K4 = (K + 3) & ~3;
+    float2 pre[QMAX];
+    // rows_fast: thread value q is sample (tid >> 5) + 8 q of row tid & 31
+    // (the tile walked rows fastest); else 8 threads per row, value q is
+    // sample (tid & 7) + 8 q of row tid / 8; rows are decoded once
+    auto load_tile = [&](int64_t tile) {
+        const int64_t rbase = tile * 32;
+        if (P::rows_fast) {
+            const int64_t row = rbase + (tid & 31);
+            const bool ok = row < p.nrows;
+            const typename P::Row w = p.row_at(ok ? row : 0);
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                const int k = (tid >> 5) + 8 * q;
+                pre[q] = (q < nq && ok && k < K) ? p.at(w, k) : make_float2(0.f, 0.f);
+            }
+        } else {
+            const int64_t row = rbase + (tid >> 3);
+            const bool ok = row < p.nrows;
+            const typename P::Row w = p.row_at(ok ? row : 0);
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                const int k = (tid & 7) + 8 * q;
+                pre[q] = (q < nq && ok && k < K) ? p.at(w, k) : make_float2(0.f, 0.f);
+            }
+        }
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            if (q >= nq) break;
+            int k, rl;
+            if (P::rows_fast) {
+                k = (tid >> 5) + 8 * q;
+                rl = tid & 31;
+            } else {
+                k = (tid & 7) + 8 * q;
+                rl = tid >> 3;
+            }
+            if (k < K4) As[rl * KP + k] = pre[q];
+        }
+    };
     for (int n0 = 0; n0 < p.N; n0 += NC) {
         __syncthreads();
-        for (int base = threadIdx.x; base < K4 * NC; base += 8 * blockDim.x) {
+        for (int base = tid; base < K4 * NC; base += 8 * blockDim.x) {
             float v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -324,38 +376,14 @@ __global__ void __launch_bounds__(256) k_rowgemm_lds(P p, int col_override)
                 if (idx < K4 * NC) Bs[idx] = v[u];
             }
         }
-        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-            const int64_t rbase = tile * 32;
+        int64_t tile = blockIdx.x;
+        if (tile < ntiles) load_tile(tile);
+        for (; tile < ntiles; tile += gridDim.x) {
+            __syncthreads();  // the previous tile's MFMAs are done with As
+            store_tile();
             __syncthreads();
-            if (P::rows_fast) {
-                for (int base = threadIdx.x; base < 32 * K4; base += 4 * blockDim.x) {
-                    float2 v[4];
-                    int dst[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int idx = base + u * blockDim.x;
-                        const int k = idx >> 5, rl = idx & 31;
-                        const int64_t row = rbase + rl;
-                        dst[u] = idx < 32 * K4 ? rl * KP + k : -1;
-                        v[u] = (dst[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
-                                                                        : make_float2(0.f, 0.f);
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (dst[u] >= 0) As[dst[u]] = v[u];
-                }
-            } else {
-                // 8 threads per row: the row is decoded once, its K samples
-                // are contiguous
-                const int rl = threadIdx.x >> 3;
-                const int64_t row = rbase + rl;
-                const bool ok = row < p.nrows;
-                const typename P::Row w = p.row_at(ok ? row : 0);
-                for (int k = threadIdx.x & 7; k < K4; k += 8)
-                    As[rl * KP + k] = (ok && k < K) ? p.at(w, k) : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            const int64_t row0 = rbase + wave * 8;
+            if (tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
+            const int64_t row0 = tile * 32 + wave * 8;
             if (row0 >= p.nrows) continue;
             const float2 *arow = As + (wave * 8 + t) * KP;
             floatx4 acc[NT];
@@ -574,19 +602,35 @@ static hipError_t launch_rowgemm(const P &p, hipStream_t s, int gridy = 1, int c
         return hipGetLastError();
     }
     if (p.K <= 128) {
-        int nt = 1;
-        while (nt < 8 && 16 * nt < p.N) nt <<= 1;
-        while (nt > 1 && lds_bytes_rowgemm(p.K, nt) > 65536) nt >>= 1;
+        // column tiles: as many as N needs (at most 8, several passes
+        // beyond), fewer while the LDS exceeds 80 KB (two workgroups per CU)
+        int nt = std::min(8, (p.N + 15) / 16);
+        while (nt > 1 && lds_bytes_rowgemm(p.K, nt) > 81920) --nt;
         const int64_t ntiles = (p.nrows + 31) / 32;
         const unsigned gx = (unsigned)std::min<int64_t>(ntiles, 2048 / gridy + 1);
         dim3 grid(gx, gridy), block(256);
         const size_t lds = lds_bytes_rowgemm(p.K, nt);
-        switch (nt) {
-        case 1: hipLaunchKernelGGL((k_rowgemm_lds<P, 1>), grid, block, lds, s, p, col0); break;
-        case 2: hipLaunchKernelGGL((k_rowgemm_lds<P, 2>), grid, block, lds, s, p, col0); break;
-        case 4: hipLaunchKernelGGL((k_rowgemm_lds<P, 4>), grid, block, lds, s, p, col0); break;
-        default: hipLaunchKernelGGL((k_rowgemm_lds<P, 8>), grid, block, lds, s, p, col0); break;
-        }
+        // staging registers per thread: (K rounded up to 4) / 8, in classes
+        const int nq = (((p.K + 3) & ~3) + 7) / 8;
+        const int q = nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
+#define ROWGEMM_LDS(NTV, QV) \
+    hipLaunchKernelGGL((k_rowgemm_lds<P, NTV, QV>), grid, block, lds, s, p, col0)
+#define ROWGEMM_LDS_NT(QV)                     \
+    switch (nt) {                              \
+    case 1: ROWGEMM_LDS(1, QV); break;         \
+    case 2: ROWGEMM_LDS(2, QV); break;         \
+    case 3: ROWGEMM_LDS(3, QV); break;         \
+    case 4: ROWGEMM_LDS(4, QV); break;         \
+    case 5: ROWGEMM_LDS(5, QV); break;         \
+    case 6: ROWGEMM_LDS(6, QV); break;         \
+    case 7: ROWGEMM_LDS(7, QV); break;         \
+    default: ROWGEMM_LDS(8, QV); break;        \
+    }
+        if (q == 4) { ROWGEMM_LDS_NT(4) }
+        else if (q == 8) { ROWGEMM_LDS_NT(8) }
+        else { ROWGEMM_LDS_NT(16) }
+#undef ROWGEMM_LDS_NT
+#undef ROWGEMM_LDS
         return hipGetLastError();
     }
     const int64_t waves = (p.nrows + 7) / 8;
