@@ -81,6 +81,7 @@ struct mlfma_ops_s {
     // library streams for the concurrent schedule (near field; M2L) and
     // the events that fork and join them
     hipStream_t side[2] = {nullptr, nullptr};
+    bool near_early = false;         // concurrent: near field forked at the start
     hipEvent_t ev_fork = nullptr, ev_near = nullptr, ev_m2l = nullptr;
     std::vector<hipEvent_t> ev_S;  // per level: multipoles ready
     // captured graphs of previous calls (MLFMA_USE_GRAPH)
@@ -449,6 +450,83 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     return MLFMA_OK;
 }
 
+// The near field and the far field from the gathered charges o->qs up to
+// the leaf locals and o->near.  Concurrent schedule (side streams present,
+// not disabled): the near field runs on side[0], forked at the start
+// (o->near_early) or at the start of the downward pass, and joined on `s`
+// at the end; the M2L of each level runs on side[1].
+int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
+{
+    const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
+    const int64_t nnear = o->n * R * (field ? 3 : 1);
+    const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM) &&
+                      !(o->prof_mask & MLFMA_PROFILE_SERIAL);
+    auto near = [&]() -> int {
+        if (conc) {
+            CK(hipEventRecord(o->ev_fork, s));
+            CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
+        }
+        hipStream_t s0 = s;
+        hipStream_t s = conc ? o->side[0] : s0;
+        if (parts & MLFMA_NEAR)
+            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->n_p2p_heavy, o->pts,
+                                         o->pt_start, o->near_start, o->near_idx, o->leaf_coord,
+                                         (float)o->tree->leaf, (float)o->k, o->qs, R, field,
+                                         o->near, s));
+        else
+            LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
+        if (conc) CK(hipEventRecord(o->ev_near, s));
+        return MLFMA_OK;
+    };
+    auto none = []() -> int { return MLFMA_OK; };
+    const bool early = !conc || o->near_early;
+    if (early)
+        if (int r = near()) return r;
+    if (far) {
+        const int r2 = early ? run_far(o, R, s, conc, none) : run_far(o, R, s, conc, near);
+        if (r2) return r2;
+    }
+    if (conc) CK(hipStreamWaitEvent(s, o->ev_near, 0));
+    return MLFMA_OK;
+}
+
+// Pick where the concurrent schedule forks the near field: time the core
+// (near + far field, max_rhs right-hand sides) both ways on a scratch stream.
+int tune_schedule(mlfma_ops_s *o)
+{
+    if (!o->side[0] || o->n_lev < 3) return MLFMA_OK;
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return fail(MLFMA_EDEVICE, "tune_schedule: stream");
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 1e30f;
+    bool best_early = false;
+    int rc = MLFMA_OK;
+    for (int mode = 0; mode < 2 && rc == MLFMA_OK; ++mode) {
+        o->near_early = mode == 1;
+        rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
+        float t = 0.f;
+        if (rc == MLFMA_OK && hipEventRecord(e0, s) == hipSuccess) {
+            for (int rep = 0; rep < 3 && rc == MLFMA_OK; ++rep)
+                rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
+            if (rc == MLFMA_OK && hipEventRecord(e1, s) == hipSuccess &&
+                hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best) {
+                best = t;
+                best_early = o->near_early;
+            }
+        }
+    }
+    o->near_early = best_early;
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
 // conj_in/conj_out: -1 = follow MLFMA_CONJ in parts
 int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
               uint32_t parts, int field, hipStream_t s, int conj_in = -1, int conj_out = -1,
@@ -478,36 +556,7 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
     auto enqueue = [&]() -> int {
         const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
         LAUNCH(MLFMA_K_GATHER, dev::gather(q, dtype, o->perm, o->n, R, cin, o->qs, s));
-        const int64_t nnear = o->n * R * (field ? 3 : 1);
-        // concurrent schedule: the near field on side[0], forked after the
-        // gather and joined before L2O
-        const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM) &&
-                          !(o->prof_mask & MLFMA_PROFILE_SERIAL);
-        auto near = [&]() -> int {
-            if (conc) {
-                CK(hipEventRecord(o->ev_fork, s));
-                CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
-            }
-            hipStream_t s0 = s;
-            hipStream_t s = conc ? o->side[0] : s0;
-            if (parts & MLFMA_NEAR)
-                LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->n_p2p_heavy, o->pts,
-                                             o->pt_start, o->near_start, o->near_idx,
-                                             o->leaf_coord, (float)o->tree->leaf, (float)o->k,
-                                             o->qs, R, field, o->near, s));
-            else
-                LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
-            if (conc) CK(hipEventRecord(o->ev_near, s));
-            return MLFMA_OK;
-        };
-        // one stream: the near field first; concurrent: from the far pass
-        if (!conc)
-            if (int r = near()) return r;
-        if (far) {
-            int r2 = run_far(o, R, s, conc, near);
-            if (r2) return r2;
-        }
-        if (conc) CK(hipStreamWaitEvent(s, o->ev_near, 0));
+        if (int r = run_core(o, R, field, parts, s)) return r;
         DevLevel &leaf = o->lev[o->n_lev];
         if (far && !field && R >= 8) {
             // many right-hand sides: per-leaf product on the matrix cores
@@ -868,6 +917,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             for (int l = 3; l <= nl; ++l)
                 if (hipEventCreateWithFlags(&o->ev_S[l], hipEventDisableTiming) != hipSuccess)
                     return fail(MLFMA_EDEVICE, "precompute: event creation failed");
+            if (!(flags & MLFMA_NO_AUTOTUNE))
+                if ((r = tune_schedule(o))) return r;
         }
         return MLFMA_OK;
     }();
@@ -1044,6 +1095,10 @@ int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
                              : -1;
         return MLFMA_OK;
     }
+    if (kernel == MLFMA_K_P2P) {
+        if (max_entries >= 1) out[0] = o->side[0] ? (o->near_early ? 1 : 0) : -1;
+        return MLFMA_OK;
+    }
     return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
 }
 
@@ -1063,6 +1118,10 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
                         level);
         (kernel == MLFMA_K_INTERP ? o->lev[level].interp_variant : o->lev[level].anterp_variant) =
             variant;
+    } else if (kernel == MLFMA_K_P2P) {
+        if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (!o->side[0]) return fail(MLFMA_EINVAL, "ops_set_variant: one-stream handle has no schedule");
+        o->near_early = variant == 1;
     } else {
         return fail(MLFMA_EINVAL, "ops_set_variant: kernel %d has no variants", kernel);
     }

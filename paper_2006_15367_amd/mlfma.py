@@ -315,12 +315,14 @@ class Operators:
         return out
 
     def variants(self, kernel="m2l"):
-        """Per-level kernel variant chosen by the autotuner (-1: no kernel)."""
+        """Per-level kernel variant chosen by the autotuner (-1: no kernel).
+        kernel="p2p": one entry, where the concurrent schedule forks the near
+        field (1 at the start, 0 at the downward pass, -1 one stream)."""
         nl = self.tree.info()["n_levels"]
-        out = np.empty(nl, np.int32)
-        _check(_load().mlfma_ops_variants(self._h, KERNELS.index(kernel), out.ctypes.data, nl),
-               "mlfma_ops_variants")
-        return out.tolist()
+        out = np.full(max(nl, 1), -1, np.int32)
+        _check(_load().mlfma_ops_variants(self._h, KERNELS.index(kernel), out.ctypes.data,
+                                          out.size), "mlfma_ops_variants")
+        return out[:1].tolist() if kernel == "p2p" else out[:nl].tolist()
 
     def set_variant(self, level, variant, kernel="m2l"):
         _check(_load().mlfma_ops_set_variant(self._h, KERNELS.index(kernel), int(level),

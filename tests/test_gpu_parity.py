@@ -273,13 +273,20 @@ def test_concurrent_schedule_equals_one_stream(c1):
     n = c1["xyz"].shape[0]
     Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
     Qd = torch.from_numpy(Q).cuda()
-    for rep in range(3):
-        a = _run(c1, ops.matvec, Qd)
-        b = _run(c1, ops1.matvec, Qd)
-        assert np.array_equal(a, b), rep
-    fa = _run(c1, ops.field, Qd[:, 0].contiguous())
-    fb = _run(c1, ops1.field, Qd[:, 0].contiguous())
-    assert np.array_equal(fa, fb)
+    tuned = ops.variants("p2p")[0]
+    assert tuned in (0, 1) and ops1.variants("p2p") == [-1]
+    try:
+        for fork in (0, 1):  # near field forked at the downward pass / at the start
+            ops.set_variant(0, fork, kernel="p2p")
+            for rep in range(3):
+                a = _run(c1, ops.matvec, Qd)
+                b = _run(c1, ops1.matvec, Qd)
+                assert np.array_equal(a, b), (fork, rep)
+            fa = _run(c1, ops.field, Qd[:, 0].contiguous())
+            fb = _run(c1, ops1.field, Qd[:, 0].contiguous())
+            assert np.array_equal(fa, fb), fork
+    finally:
+        ops.set_variant(0, tuned, kernel="p2p")
 
 
 def test_graph_replays_match_eager(c1):
