@@ -396,8 +396,8 @@ k_c2m(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
         float2 acc[RC];
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] = make_float2(0.f, 0.f);
-        for (int j0 = p0; j0 < p1; j0 += 256) {
-            const int nj = min(256, p1 - j0);
+        for (int j0 = p0; j0 < p1; j0 += (int)blockDim.x) {
+            const int nj = min((int)blockDim.x, p1 - j0);
             __syncthreads();
             if ((int)threadIdx.x < nj) {
                 sp[threadIdx.x] = pts[j0 + threadIdx.x];
@@ -516,14 +516,17 @@ hipError_t c2m(const float4 *pts, const int32_t *pt_start, int64_t nleaf,
                            khat_w, (int)K, kw, qs, R, S);
         return hipGetLastError();
     }
+    // one thread per sample: whole waves up to 256 threads (162 leaf samples
+    // take 3 waves, not 4)
+    const dim3 blk((unsigned)std::min<int64_t>(256, (K + 63) / 64 * 64));
     if (R == 1) {
-        hipLaunchKernelGGL(k_c2m<1>, dim3((unsigned)nleaf, 1), dim3(256), 0, s, pts, pt_start,
+        hipLaunchKernelGGL(k_c2m<1>, dim3((unsigned)nleaf, 1), blk, 0, s, pts, pt_start,
                            khat_w, K, kw, qs, R, S);
     } else if (R <= 4) {
-        hipLaunchKernelGGL(k_c2m<4>, dim3((unsigned)nleaf, 1), dim3(256), 0, s, pts,
+        hipLaunchKernelGGL(k_c2m<4>, dim3((unsigned)nleaf, 1), blk, 0, s, pts,
                            pt_start, khat_w, K, kw, qs, R, S);
     } else {
-        hipLaunchKernelGGL(k_c2m<16>, dim3((unsigned)nleaf, (R + 15) / 16), dim3(256), 0, s, pts,
+        hipLaunchKernelGGL(k_c2m<16>, dim3((unsigned)nleaf, (R + 15) / 16), blk, 0, s, pts,
                            pt_start, khat_w, K, kw, qs, R, S);
     }
     return hipGetLastError();
@@ -593,28 +596,47 @@ __global__ void k_l2o_scatter(const float4 *__restrict__ pts,
     if (far) {
         const float4 d = pts[s];
         const float2 *Lb = L + ((int64_t)pt_leaf[s] * R + r0) * K;
-        for (int64_t k = 0; k < K; ++k) {
-            const float4 kh = khat_w[k];
+        // samples in batches of 8: the batch's loads are issued together
+        // (a missing right-hand side re-reads the first and is not added)
+        auto sample = [&](const float4 &kh, const float2 (&lv)[RC]) {
             float sn, cs;
             __sincosf(kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
             const float2 e = make_float2(cs * kh.w, sn * kh.w);
 #pragma unroll
             for (int c = 0; c < RC; ++c) {
-                if (c < rc) {
-                    const float2 v = cmul(e, Lb[c * K + k]);
-                    if (FIELD) {
-                        const float kd[3] = {kh.x, kh.y, kh.z};
+                const float2 v = cmul(e, lv[c]);
+                const float m = c < rc ? 1.f : 0.f;
+                if (FIELD) {
+                    const float kd[3] = {kh.x * m, kh.y * m, kh.z * m};
 #pragma unroll
-                        for (int a = 0; a < NA; ++a) {
-                            acc[c][a].x = fmaf(v.x, kd[a], acc[c][a].x);
-                            acc[c][a].y = fmaf(v.y, kd[a], acc[c][a].y);
-                        }
-                    } else {
-                        acc[c][0].x += v.x;
-                        acc[c][0].y += v.y;
+                    for (int a = 0; a < NA; ++a) {
+                        acc[c][a].x = fmaf(v.x, kd[a], acc[c][a].x);
+                        acc[c][a].y = fmaf(v.y, kd[a], acc[c][a].y);
                     }
+                } else {
+                    acc[c][0].x = fmaf(v.x, m, acc[c][0].x);
+                    acc[c][0].y = fmaf(v.y, m, acc[c][0].y);
                 }
             }
+        };
+        int64_t k = 0;
+        for (; k + 8 <= K; k += 8) {
+            float4 kh[8];
+            float2 lv[8][RC];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                kh[u] = khat_w[k + u];
+#pragma unroll
+                for (int c = 0; c < RC; ++c) lv[u][c] = Lb[(c < rc ? c : 0) * K + k + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sample(kh[u], lv[u]);
+        }
+        for (; k < K; ++k) {
+            float2 lv[RC];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) lv[c] = Lb[(c < rc ? c : 0) * K + k];
+            sample(khat_w[k], lv);
         }
         // potential: (i kw / 4pi) acc;  gradient: (i kw)^2 / 4pi = -kw^2/4pi
 #pragma unroll
