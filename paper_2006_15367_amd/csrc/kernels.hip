@@ -137,38 +137,75 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
         __syncthreads();
     };
 
-    // stage the near sources, 64 NW at a time
-    int fill = 0;
-    const int e1 = near_start[b + 1];
-    for (int e = near_start[b]; e < e1; ++e) {
-        const int nb = near_idx[e];
-        const float ox = (float)(coord[3 * nb] - cbx) * leaf;
-        const float oy = (float)(coord[3 * nb + 1] - cby) * leaf;
-        const float oz = (float)(coord[3 * nb + 2] - cbz) * leaf;
-        const int j1 = pt_start[nb + 1];
-        for (int j = pt_start[nb]; j < j1; j += NT) {
-            const int cnt = min(NT, j1 - j);
-            int done = 0;
-            while (done < cnt) {
-                const int take = min(cnt - done, CH - fill);
-                if (tid < take) {
-                    const float4 pj = pts[j + done + tid];
-                    sp[fill + tid] = make_float4(pj.x + ox, pj.y + oy, pj.z + oz, 0.f);
+    // stage the near sources CH at a time.  The metadata of the (at most 27)
+    // near leaves go to a table in LDS first (one load per lane, an
+    // exclusive prefix of their point counts by shuffles); a staging slot
+    // then finds its leaf by binary search in the table, and all slots'
+    // loads of a chunk are issued together.
+    __shared__ int nb_excl[32], nb_first[32];
+    __shared__ float4 nb_off[32];
+    __shared__ int nb_total;
+    const int e0 = near_start[b];
+    const int nn = min(32, near_start[b + 1] - e0);
+    if (tid < 64) {
+        int cnt = 0, first = 0;
+        float4 off = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (tid < nn) {
+            const int nb = near_idx[e0 + tid];
+            first = pt_start[nb];
+            cnt = pt_start[nb + 1] - first;
+            off = make_float4((float)(coord[3 * nb] - cbx) * leaf,
+                              (float)(coord[3 * nb + 1] - cby) * leaf,
+                              (float)(coord[3 * nb + 2] - cbz) * leaf, 0.f);
+        }
+        int inc = cnt;
 #pragma unroll
-                    for (int c = 0; c < RC; ++c)
-                        sq[(fill + tid) * RC + c] = c < rc ? qs[(int64_t)(j + done + tid) * R + r0 + c]
-                                                           : make_float2(0.f, 0.f);
-                }
-                fill += take;
-                done += take;
-                if (fill == CH) {
-                    process(fill);
-                    fill = 0;
-                }
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(inc, d, 64);
+            if (tid >= d) inc += v;
+        }
+        if (tid < 32) {
+            nb_excl[tid] = tid < nn ? inc - cnt : 0x7fffffff;
+            nb_first[tid] = first;
+            nb_off[tid] = off;
+        }
+        if (tid == 63) nb_total = inc;
+    }
+    __syncthreads();
+    const int total = nb_total;
+    constexpr int SPT = CH / NT;  // staging slots per thread
+    for (int c0 = 0; c0 < total; c0 += CH) {
+        const int n = min(CH, total - c0);
+        float4 pv[SPT];
+        float2 qv[SPT][RC];
+        int slot[SPT];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            slot[u] = tid + u * NT;
+            const int gidx = c0 + slot[u];
+            int e = 0;
+#pragma unroll
+            for (int st = 16; st >= 1; st >>= 1)
+                if (nb_excl[e + st] <= gidx) e += st;
+            const bool ok = slot[u] < n;
+            const int j = ok ? nb_first[e] + (gidx - nb_excl[e]) : 0;
+            const float4 o = nb_off[e];
+            const float4 pj = ok ? pts[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            pv[u] = make_float4(pj.x + o.x, pj.y + o.y, pj.z + o.z, 0.f);
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                qv[u][c] = (ok && c < rc) ? qs[(int64_t)j * R + r0 + c] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            if (slot[u] < n) {
+                sp[slot[u]] = pv[u];
+#pragma unroll
+                for (int c = 0; c < RC; ++c) sq[slot[u] * RC + c] = qv[u][c];
             }
         }
+        process(n);
     }
-    process(fill);
     // add the G partial sums of each target: lanes t, t+T, ... inside a wave
     // by shuffles, then the waves through LDS
     const int GW = Tp < 64 ? 64 / Tp : 1;  // groups per wave
