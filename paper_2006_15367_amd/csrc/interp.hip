@@ -834,9 +834,16 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M, const int3
     // orders per step: one step per child up to 68 orders
     const int mkb = M <= 20 ? 5 : M <= 28 ? 7 : M <= 44 ? 11 : 17;
     const int mp = (M + 4 * mkb - 1) / (4 * mkb) * 4 * mkb;
-    int nt = pick_nt(mp, nphp);
-    while (nt > 1 && waves * ((nphp + 16 * nt - 1) / (16 * nt)) < 2048) nt >>= 1;
-    const int nch = (nphp + 16 * nt - 1) / (16 * nt);
+    // column chunks of 16 NT (NT = 1..8, as even as nphp allows): the
+    // fewest chunks that give >= 2048 waves and keep the slice <= 64 KB
+    int nch = 1, nt = 8;
+    for (;; ++nch) {
+        nt = (nphp + 16 * nch - 1) / (16 * nch);
+        if (nt > 8) continue;
+        if ((size_t)mp * 16 * nt * sizeof(float) > 65536 && nt > 1) continue;
+        if (waves * nch >= 2048 || nt == 1) break;
+    }
+    nch = (nphp + 16 * nt - 1) / (16 * nt);  // the chunk count the kernel derives
     dim3 grid((unsigned)(waves_to_blocks(waves) * nch)), block(256);
     const size_t lds = (size_t)mp * 16 * nt * sizeof(float);
 #define M2M_S3(NTV, MKBV)                                                                        \
@@ -846,7 +853,11 @@ hipError_t interp_s3(int64_t nboxp, int R, int nthp, int nphp, int M, const int3
     switch (nt) {                        \
     case 1: M2M_S3(1, MKBV); break;      \
     case 2: M2M_S3(2, MKBV); break;      \
+    case 3: M2M_S3(3, MKBV); break;      \
     case 4: M2M_S3(4, MKBV); break;      \
+    case 5: M2M_S3(5, MKBV); break;      \
+    case 6: M2M_S3(6, MKBV); break;      \
+    case 7: M2M_S3(7, MKBV); break;      \
     default: M2M_S3(8, MKBV); break;     \
     }
     switch (mkb) {
