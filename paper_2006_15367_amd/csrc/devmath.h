@@ -28,5 +28,21 @@ __device__ __forceinline__ float2 cfma_conj(float2 a, float2 b, float2 c)
     return c;
 }
 
+// 1 / |r| from r2 = |r|^2: the hardware reciprocal square root (without
+// the rescaling rsqrtf applies to subnormal inputs; a positive r2 below the
+// smallest normal float is taken as that float) and 0 for r2 == 0, the
+// coincident point, which the Green's function sums leave out
+__device__ __forceinline__ float rsq_or_zero(float r2)
+{
+    const float y = __builtin_amdgcn_rsqf(fmaxf(r2, 1.17549435e-38f));
+    return r2 > 0.f ? y : 0.f;
+}
+// sin and cos of 2 pi t (t in turns) on the hardware sine / cosine units
+__device__ __forceinline__ void sincos_turns(float t, float *s, float *c)
+{
+    *s = __builtin_amdgcn_sinf(t);
+    *c = __builtin_amdgcn_cosf(t);
+}
+
 }  // namespace dev
 }  // namespace mlfma

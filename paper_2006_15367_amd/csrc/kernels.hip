@@ -79,6 +79,7 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
     constexpr int NA = FIELD ? 3 : 1;
     constexpr int CH = 256;
     constexpr int NT = 64 * NW;
+    const float kwt = kw * 0.159154943f;  // wavenumber in turns per unit length
     __shared__ float4 sp[CH];
     __shared__ float2 sq[CH * RC];
     const int tid = threadIdx.x;
@@ -109,9 +110,9 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
             const float dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             // coincident point (self): r2 == 0 contributes nothing
-            const float rinv = r2 > 0.f ? rsqrtf(r2) : 0.f;
+            const float rinv = rsq_or_zero(r2);
             float sn, cs;
-            __sincosf(kw * (r2 * rinv), &sn, &cs);
+            sincos_turns(kwt * (r2 * rinv), &sn, &cs);
             float2 gk = make_float2(cs * rinv, sn * rinv);
             if (FIELD) {
                 // grad G = G (ik - 1/r) r_vec / r
@@ -303,6 +304,7 @@ k_p2p_mfma(const int2 *__restrict__ items, const float4 *__restrict__ pts,
            float kw, const float2 *__restrict__ qs, int R, float2 *__restrict__ out)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
+    const float kwt = kw * 0.159154943f;  // wavenumber in turns per unit length
     __shared__ float4 sp[64];
     __shared__ int sid[64];
     __shared__ float4 tp[16];
@@ -354,9 +356,9 @@ k_p2p_mfma(const int2 *__restrict__ items, const float4 *__restrict__ pts,
                     const float4 pi = tp[t], sj = sp[sx];
                     const float dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
                     const float r2 = dx * dx + dy * dy + dz * dz;
-                    const float rinv = r2 > 0.f ? rsqrtf(r2) : 0.f;
+                    const float rinv = rsq_or_zero(r2);
                     float sn, cs;
-                    __sincosf(kw * (r2 * rinv), &sn, &cs);
+                    sincos_turns(kwt * (r2 * rinv), &sn, &cs);
                     gr = cs * rinv;
                     gi = sn * rinv;
                 }
@@ -420,6 +422,7 @@ k_c2m(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
       const float4 *__restrict__ khat_w, int64_t K, float kw,
       const float2 *__restrict__ qs, int R, float2 *__restrict__ S)
 {
+    const float kwt = kw * 0.159154943f;  // wavenumber in turns per unit length
     __shared__ float4 sp[256];
     __shared__ float2 sq[256 * RC];
     const int64_t b = blockIdx.x;
@@ -446,9 +449,9 @@ k_c2m(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
             __syncthreads();
             for (int j = 0; j < nj; ++j) {
                 const float4 d = sp[j];
-                const float ph = -kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z);
+                const float ph = -kwt * (kh.x * d.x + kh.y * d.y + kh.z * d.z);
                 float sn, cs;
-                __sincosf(ph, &sn, &cs);
+                sincos_turns(ph, &sn, &cs);
                 const float2 e = make_float2(cs, sn);
 #pragma unroll
                 for (int c = 0; c < RC; ++c) acc[c] = cfma(sq[j * RC + c], e, acc[c]);
@@ -475,6 +478,7 @@ k_c2m_mfma(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
            const float4 *__restrict__ khat_w, int K, float kw, const float2 *__restrict__ qs,
            int R, float2 *__restrict__ S)
 {
+    const float kwt = kw * 0.159154943f;  // wavenumber in turns per unit length
     typedef float f4 __attribute__((ext_vector_type(4)));
     extern __shared__ float Fs[];  // [16][2K]: F_re in columns 0..K-1, F_im in K..2K-1
     const int64_t b = blockIdx.x;
@@ -501,7 +505,7 @@ k_c2m_mfma(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
             for (int p = 0; p < 16; ++p) {
                 const float4 d = Pt[p];
                 float sn, cs;
-                __sincosf(-kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
+                sincos_turns(-kwt * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
                 const bool pv = t0 + p < np;
                 Fs[p * 2 * K + k] = pv ? cs : 0.f;
                 Fs[p * 2 * K + K + k] = pv ? sn : 0.f;
@@ -616,6 +620,7 @@ __global__ void k_l2o_scatter(const float4 *__restrict__ pts,
                               const float2 *__restrict__ L, const float2 *__restrict__ near,
                               int64_t n, int R, int far, int conj_out, Tout *__restrict__ out)
 {
+    const float kwt = kw * 0.159154943f;  // wavenumber in turns per unit length
     // one thread per (point, chunk of RC right-hand sides): the plane-wave
     // factor of each sample is computed once and used for the whole chunk
     constexpr int NA = FIELD ? 3 : 1;
@@ -637,7 +642,7 @@ __global__ void k_l2o_scatter(const float4 *__restrict__ pts,
         // (a missing right-hand side re-reads the first and is not added)
         auto sample = [&](const float4 &kh, const float2 (&lv)[RC]) {
             float sn, cs;
-            __sincosf(kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
+            sincos_turns(kwt * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
             const float2 e = make_float2(cs * kh.w, sn * kh.w);
 #pragma unroll
             for (int c = 0; c < RC; ++c) {
@@ -724,6 +729,7 @@ k_l2o_mfma(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
            const float2 *__restrict__ L, const float2 *__restrict__ near, int R, int conj_out,
            Tout *__restrict__ out)
 {
+    const float kwt = kw * 0.159154943f;  // wavenumber in turns per unit length
     extern __shared__ float Es[];  // [16][2K]: E_re in columns 0..K-1, E_im in K..2K-1
     __shared__ float4 Pt[16];      // the points of the tile
     const int64_t b = blockIdx.x;
@@ -745,7 +751,7 @@ k_l2o_mfma(const float4 *__restrict__ pts, const int32_t *__restrict__ pt_start,
             for (int p = 0; p < 16; ++p) {
                 const float4 d = Pt[p];
                 float sn, cs;
-                __sincosf(kw * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
+                sincos_turns(kwt * (kh.x * d.x + kh.y * d.y + kh.z * d.z), &sn, &cs);
                 const bool pv = t0 + p < np;
                 Es[p * 2 * K + k] = pv ? cs * kh.w : 0.f;
                 Es[p * 2 * K + K + k] = pv ? sn * kh.w : 0.f;
