@@ -38,6 +38,12 @@ BOUND = {"gather": "hbm", "p2p": "alu", "c2m": "alu", "interp_s1": "mfma",
          "anterp": "mfma"}
 
 
+# shift of the second-kind system solved by the GMRES leg: of the order of
+# the operator's spectral radius at these point densities (about 330 points
+# per square wavelength on the spheres)
+GMRES_SHIFT = 1000j
+
+
 def algorithmic_work(tinfo, levels, R, onepass_up=None, onepass_down=None):
     """Algorithmic bytes and flops of each kernel for one step with R
     right-hand sides (complex64 = 8 bytes; a complex multiply-add = 8 flops;
@@ -280,6 +286,23 @@ def main():
         torch.cuda.synchronize()
         adj_ms = (time.perf_counter() - ta) * 1e3 / args.steps
 
+        # iterative solve of (shift I + A) x = q by restarted GMRES on the
+        # same operator (one right-hand side); the first call allocates the
+        # Krylov workspace and is not timed
+        gmres = None
+        if R == 1:
+            ops.solve(qd, GMRES_SHIFT, restart=30, max_iters=2, tol=1e-5, stream=st)
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            _, g_it, g_rr = ops.solve(qd, GMRES_SHIFT, restart=30, max_iters=300, tol=1e-5,
+                                      stream=st)
+            g_ms = (time.perf_counter() - tg) * 1e3
+            gmres = {"system": "(shift I + A) x = q, shift = %gi" % GMRES_SHIFT.imag,
+                     "restart": 30, "tol": 1e-5, "iterations": g_it,
+                     "rel_residual": g_rr, "ms": round(g_ms, 3),
+                     "ms_per_iteration": round(g_ms / max(1, g_it), 4),
+                     "matvec_share": round(g_it * ms_per_step / g_ms, 3)}
+
     work = algorithmic_work(tinfo, levels, R, ops.variants("interp"), ops.variants("anterp"))
     rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
     alone = roofline(dominant, work[dominant], dom_alone[0] / args.steps, launches, args.bf16x3)
@@ -310,6 +333,7 @@ def main():
         "onepass_interp_per_level": ops.variants("interp"),
         "onepass_anterp_per_level": ops.variants("anterp"),
         "roofline": rl,
+        "gmres": gmres,
     }
     if not args.no_cpu_baseline:
         phi_np = phi.cpu().numpy().astype(np.complex128)

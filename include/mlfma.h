@@ -225,6 +225,37 @@ int mlfma_position_gradient(mlfma_ops_t ops, const void *q, const void *g, void 
                             int64_t nrhs, int dtype, void *stream);
 
 /* NULL is a no-op.  Wait for outstanding work on the handle's streams first. */
+/*
+ * Iterative solve of the second-kind system (shift I + A) x = b, A the
+ * potential operator of `ops` (phi = A q as mlfma_matvec computes it), for
+ * one right-hand side: the iterative solver of the integral equations that
+ * the potential sum comes from (Sec. 1, Sec. 2).  Restarted GMRES(restart)
+ * (Saad and Schultz): Krylov basis in complex64 on the device, classical
+ * Gram-Schmidt applied twice with FP64 coefficients, Givens rotations and
+ * the small least-squares problem on the host in FP64.
+ *   b, x       device, [n] complex64, caller order; x holds the initial
+ *              guess on entry (zeros allowed) and the solution on exit.
+ *              b and x must not overlap.
+ *   shift      complex shift (shift_re + i shift_im) of the identity.
+ *   restart    Krylov dimension per cycle, 1..500.
+ *   max_iters  total operator applications allowed (0: only the residual
+ *              of the initial guess is computed).
+ *   tol        target ||b - (shift I + A) x|| / ||b|| (> 0).
+ *   iters, rel_residual  host outputs (may be NULL): operator applications
+ *              used, and the relative residual of the returned x,
+ *              recomputed with the operator (not the GMRES estimate).
+ * Not converging within max_iters is not an error: MLFMA_OK is returned and
+ * rel_residual tells.  Synchronises `stream` (the residual checks run on the
+ * host).  The workspace ((restart + 2) n complex64 and small buffers) is
+ * allocated on the first call that needs it and kept by the handle; it is
+ * counted against mlfma_set_device_memory_limit.
+ * Errors: MLFMA_EINVAL (null or aliased buffers, restart, tol, shift),
+ * MLFMA_ENOMEM, MLFMA_EDEVICE.
+ */
+int mlfma_solve_gmres(mlfma_ops_t ops, const void *b, void *x, double shift_re,
+                      double shift_im, int restart, int max_iters, double tol,
+                      int *iters, double *rel_residual, void *stream);
+
 void mlfma_destroy_ops(mlfma_ops_t ops);
 void mlfma_destroy_tree(mlfma_tree_t t);
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -82,6 +83,12 @@ struct mlfma_ops_s {
     // the events that fork and join them
     hipStream_t side[2] = {nullptr, nullptr};
     bool near_early = false;         // concurrent: near field forked at the start
+    // GMRES workspace: Krylov basis [(gm_cap + 1) x n], work vector,
+    // dot-product partials, coefficient vector (allocated on first solve)
+    int gm_cap = 0;
+    float2 *gm_V = nullptr, *gm_w = nullptr;
+    double2 *gm_part = nullptr, *gm_c = nullptr;
+    int64_t planned_bytes = 0;       // device bytes of the precompute
     hipEvent_t ev_fork = nullptr, ev_near = nullptr, ev_m2l = nullptr;
     std::vector<hipEvent_t> ev_S;  // per level: multipoles ready
     // captured graphs of previous calls (MLFMA_USE_GRAPH)
@@ -721,6 +728,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         }
         pl.add(scratch * 8 * 2);
     }
+    o->planned_bytes = pl.bytes;
     const int64_t lim = g_mem_limit.load();
     if (lim > 0 && pl.bytes > lim) {
         rc = fail(MLFMA_ENOMEM, "precompute: needs %lld device bytes, limit is %lld",
@@ -948,6 +956,190 @@ int mlfma_matvec_ex(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs, int
                     uint32_t parts, void *stream)
 {
     return do_matvec(ops, q, phi, nrhs, dtype, parts, 0, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------- GMRES solve --
+namespace {
+
+void free_alloc(mlfma_ops_s *o, void *p)
+{
+    if (!p) return;
+    auto it = std::find(o->allocs.begin(), o->allocs.end(), p);
+    if (it != o->allocs.end()) o->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+int gm_workspace(mlfma_ops_s *o, int m)
+{
+    if (m <= o->gm_cap) return MLFMA_OK;
+    free_alloc(o, o->gm_V);
+    free_alloc(o, o->gm_w);
+    free_alloc(o, o->gm_part);
+    free_alloc(o, o->gm_c);
+    o->gm_V = o->gm_w = nullptr;
+    o->gm_part = o->gm_c = nullptr;
+    o->gm_cap = 0;
+    const int64_t n = o->n, nb = dev::gm_dot_blocks(n);
+    const int64_t bytes = ((int64_t)(m + 2) * n) * (int64_t)sizeof(float2) +
+                          (int64_t)(m + 1) * nb * (int64_t)sizeof(double2) +
+                          (int64_t)(m + 1) * (int64_t)sizeof(double2);
+    const int64_t lim = g_mem_limit.load();
+    if (lim > 0 && o->planned_bytes + bytes > lim)
+        return fail(MLFMA_ENOMEM, "solve_gmres: workspace of %lld bytes exceeds the limit of %lld",
+                    (long long)bytes, (long long)lim);
+    int r;
+    if ((r = dalloc(o, &o->gm_V, (int64_t)(m + 1) * n))) return r;
+    if ((r = dalloc(o, &o->gm_w, n))) return r;
+    if ((r = dalloc(o, &o->gm_part, (int64_t)(m + 1) * nb))) return r;
+    if ((r = dalloc(o, &o->gm_c, (int64_t)(m + 1)))) return r;
+    o->gm_cap = m;
+    return MLFMA_OK;
+}
+
+}  // namespace
+
+int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, double shift_im,
+                      int restart, int max_iters, double tol, int *iters, double *rel_residual,
+                      void *stream)
+{
+    typedef std::complex<double> cd;
+    if (iters) *iters = 0;
+    if (rel_residual) *rel_residual = 0.0;
+    if (restart < 1 || restart > 500)
+        return fail(MLFMA_EINVAL, "solve_gmres: restart %d outside 1..500", restart);
+    if (max_iters < 0) return fail(MLFMA_EINVAL, "solve_gmres: max_iters < 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MLFMA_EINVAL, "solve_gmres: tol must be > 0");
+    if (!std::isfinite(shift_re) || !std::isfinite(shift_im))
+        return fail(MLFMA_EINVAL, "solve_gmres: shift is not finite");
+    if (!o) return fail(MLFMA_EINVAL, "solve_gmres: ops handle is NULL");
+    if (o->n == 0) return MLFMA_OK;
+    if (!b || !x) return fail(MLFMA_EINVAL, "solve_gmres: null buffer");
+    if (b == x) return fail(MLFMA_EINVAL, "solve_gmres: b and x must not alias");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(MLFMA_EDEVICE, "hipGetDevice failed");
+    if (cur != o->device && hipSetDevice(o->device) != hipSuccess)
+        return fail(MLFMA_EDEVICE, "hipSetDevice(%d) failed", o->device);
+    const int m = restart;
+    int rc = gm_workspace(o, m);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = o->n;
+    const int nb = dev::gm_dot_blocks(n);
+    const float2 *bv = (const float2 *)b;
+    float2 *xv = (float2 *)x, *V = o->gm_V, *w = o->gm_w;
+    auto row = [&](int i) { return V + (int64_t)i * n; };
+    std::vector<double2> part((size_t)(m + 1) * nb), coef(m + 1);
+    // out[i] = <V_i, u> for i < cnt (FP64 sums of the block partials)
+    auto dots = [&](const float2 *Vb, int cnt, const float2 *u, cd *out) -> int {
+        CK(dev::gm_dots(Vb, n, cnt, u, n, nb, o->gm_part, s));
+        CK(hipMemcpyAsync(part.data(), o->gm_part, (size_t)cnt * nb * sizeof(double2),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        for (int i = 0; i < cnt; ++i) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                re += part[(size_t)i * nb + k].x;
+                im += part[(size_t)i * nb + k].y;
+            }
+            out[i] = cd(re, im);
+        }
+        return MLFMA_OK;
+    };
+    auto norm = [&](const float2 *u, double *out) -> int {
+        cd d;
+        if (int r = dots(u, 1, u, &d)) return r;
+        *out = std::sqrt(std::max(0.0, d.real()));
+        return MLFMA_OK;
+    };
+    // u <- u + sign * sum_{i < cnt} V_i c_i
+    auto combine = [&](float2 *u, int cnt, const cd *c, double sign) -> int {
+        for (int i = 0; i < cnt; ++i) coef[i] = make_double2(c[i].real(), c[i].imag());
+        CK(hipMemcpyAsync(o->gm_c, coef.data(), (size_t)cnt * sizeof(double2),
+                          hipMemcpyHostToDevice, s));
+        CK(dev::gm_combine(u, V, n, cnt, o->gm_c, sign, n, s));
+        return MLFMA_OK;
+    };
+    // y <- (shift I + A) v
+    auto op = [&](const float2 *v, float2 *y) -> int {
+        if (int r = do_matvec(o, v, y, 1, MLFMA_C64, MLFMA_NEAR | MLFMA_FAR, 0, s)) return r;
+        CK(dev::gm_axpby(y, make_double2(shift_re, shift_im), v, make_double2(1.0, 0.0), n, s));
+        return MLFMA_OK;
+    };
+    double bnorm = 0.0;
+    if ((rc = norm(bv, &bnorm))) return rc;
+    if (bnorm == 0.0) {
+        CK(dev::gm_axpby(xv, make_double2(0.0, 0.0), xv, make_double2(0.0, 0.0), n, s));
+        CK(hipStreamSynchronize(s));
+        return MLFMA_OK;
+    }
+    std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h(m + 1), y(m);
+    auto Hat = [&](int i, int j) -> cd & { return H[(size_t)i * m + j]; };
+    int total = 0;
+    double relres = 0.0;
+    for (;;) {
+        // true residual r = b - (shift I + A) x in V_0
+        if ((rc = op(xv, w))) return rc;
+        CK(dev::gm_axpby(row(0), make_double2(1.0, 0.0), bv, make_double2(0.0, 0.0), n, s));
+        CK(dev::gm_axpby(row(0), make_double2(-1.0, 0.0), w, make_double2(1.0, 0.0), n, s));
+        double beta = 0.0;
+        if ((rc = norm(row(0), &beta))) return rc;
+        relres = beta / bnorm;
+        if (relres <= tol || total >= max_iters || beta == 0.0) break;
+        CK(dev::gm_axpby(row(0), make_double2(1.0 / beta, 0.0), row(0), make_double2(0.0, 0.0), n, s));
+        std::fill(g.begin(), g.end(), cd(0.0));
+        std::fill(H.begin(), H.end(), cd(0.0));
+        g[0] = beta;
+        int j = 0;
+        for (; j < m && total < max_iters;) {
+            if ((rc = op(row(j), w))) return rc;
+            ++total;
+            // classical Gram-Schmidt, applied twice
+            for (int pass = 0; pass < 2; ++pass) {
+                if ((rc = dots(V, j + 1, w, h.data()))) return rc;
+                if ((rc = combine(w, j + 1, h.data(), -1.0))) return rc;
+                for (int i = 0; i <= j; ++i) Hat(i, j) += h[i];
+            }
+            double hn = 0.0;
+            if ((rc = norm(w, &hn))) return rc;
+            Hat(j + 1, j) = hn;
+            if (hn > 0.0)
+                CK(dev::gm_axpby(row(j + 1), make_double2(1.0 / hn, 0.0), w, make_double2(0.0, 0.0),
+                                 n, s));
+            // previous rotations on column j, then the one that zeroes H[j+1][j]
+            for (int i = 0; i < j; ++i) {
+                const cd a = Hat(i, j), c = Hat(i + 1, j);
+                Hat(i, j) = cs[i] * a + sn[i] * c;
+                Hat(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * c;
+            }
+            const cd a = Hat(j, j), c = Hat(j + 1, j);
+            const double t = std::sqrt(std::norm(a) + std::norm(c));
+            if (std::abs(a) == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = 1.0;
+            } else {
+                cs[j] = std::abs(a) / t;
+                sn[j] = (a / std::abs(a)) * std::conj(c) / t;
+            }
+            Hat(j, j) = cs[j] * a + sn[j] * c;
+            Hat(j + 1, j) = 0.0;
+            g[j + 1] = -std::conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            ++j;
+            if (std::abs(g[j]) / bnorm <= tol || hn == 0.0) break;
+        }
+        // x += V y, H y = g (upper triangular, j columns)
+        for (int i = j - 1; i >= 0; --i) {
+            cd acc = g[i];
+            for (int k = i + 1; k < j; ++k) acc -= Hat(i, k) * y[k];
+            y[i] = Hat(i, i) != 0.0 ? acc / Hat(i, i) : cd(0.0);
+        }
+        if (j > 0)
+            if ((rc = combine(xv, j, y.data(), 1.0))) return rc;
+    }
+    CK(hipStreamSynchronize(s));
+    if (iters) *iters = total;
+    if (rel_residual) *rel_residual = relres;
+    return MLFMA_OK;
 }
 
 int mlfma_field(mlfma_ops_t ops, const void *q, void *grad, int64_t nrhs, int dtype,

@@ -129,5 +129,16 @@ hipError_t l2o_leaf_mfma(const float4 *pts, const int32_t *pt_start, int64_t nle
                          const float2 *L, const float2 *near, int R, int conj_out, int dtype,
                          void *out, hipStream_t s);
 
+// GMRES vector kernels (complex64 vectors, FP64 coefficients):
+// partial[i * nb + blk] = block partial of sum_j conj(V[i][j]) w[j], i < m
+// (nb = gm_dot_blocks(n) blocks; the host adds the partials);
+// w += sign * sum_{i < m} V[i] c[i] (c in device memory); y = a x + b y
+int gm_dot_blocks(int64_t n);
+hipError_t gm_dots(const float2 *V, int64_t ldv, int m, const float2 *w, int64_t n, int nb,
+                   double2 *partial, hipStream_t s);
+hipError_t gm_combine(float2 *w, const float2 *V, int64_t ldv, int m, const double2 *c,
+                      double sign, int64_t n, hipStream_t s);
+hipError_t gm_axpby(float2 *y, double2 a, const float2 *x, double2 b, int64_t n, hipStream_t s);
+
 }  // namespace dev
 }  // namespace mlfma
