@@ -231,8 +231,9 @@ int mlfma_position_gradient(mlfma_ops_t ops, const void *q, const void *g, void 
  * one right-hand side: the iterative solver of the integral equations that
  * the potential sum comes from (Sec. 1, Sec. 2).  Restarted GMRES(restart)
  * (Saad and Schultz): Krylov basis in complex64 on the device, classical
- * Gram-Schmidt applied twice with FP64 coefficients, Givens rotations and
- * the small least-squares problem on the host in FP64.
+ * Gram-Schmidt with FP64 coefficients (repeated when it cancels most of the
+ * new vector), Givens rotations and the small least-squares problem on the
+ * host in FP64.
  *   b, x       device, [n] complex64, caller order; x holds the initial
  *              guess on entry (zeros allowed) and the solution on exit.
  *              b and x must not overlap.

@@ -1045,6 +1045,24 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
         }
         return MLFMA_OK;
     };
+    // out[i] = <V_i, u> for i < cnt and *uu = <u, u>, one host round trip
+    auto dots_norm = [&](int cnt, const float2 *u, cd *out, double *uu) -> int {
+        CK(dev::gm_dots(V, n, cnt, u, n, nb, o->gm_part, s));
+        CK(dev::gm_dots(u, n, 1, u, n, nb, o->gm_part + (size_t)cnt * nb, s));
+        CK(hipMemcpyAsync(part.data(), o->gm_part, (size_t)(cnt + 1) * nb * sizeof(double2),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        for (int i = 0; i <= cnt; ++i) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                re += part[(size_t)i * nb + k].x;
+                im += part[(size_t)i * nb + k].y;
+            }
+            if (i < cnt) out[i] = cd(re, im);
+            else *uu = re;
+        }
+        return MLFMA_OK;
+    };
     auto norm = [&](const float2 *u, double *out) -> int {
         cd d;
         if (int r = dots(u, 1, u, &d)) return r;
@@ -1093,14 +1111,27 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
         for (; j < m && total < max_iters;) {
             if ((rc = op(row(j), w))) return rc;
             ++total;
-            // classical Gram-Schmidt, applied twice
-            for (int pass = 0; pass < 2; ++pass) {
+            // classical Gram-Schmidt, repeated once when the projection
+            // removed most of w (norm ratio below 1/sqrt(2): "twice is
+            // enough", Kahan and Parlett), so the basis stays orthonormal
+            // (the norm after a pass is ||w||^2 - sum |h_i|^2 for the
+            // orthonormal basis; the repeated pass measures it directly)
+            double ww = 0.0, hn = 0.0;
+            if ((rc = dots_norm(j + 1, w, h.data(), &ww))) return rc;
+            if ((rc = combine(w, j + 1, h.data(), -1.0))) return rc;
+            double hh = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                Hat(i, j) += h[i];
+                hh += std::norm(h[i]);
+            }
+            if (ww - hh > 0.5 * ww) {
+                hn = std::sqrt(ww - hh);
+            } else {
                 if ((rc = dots(V, j + 1, w, h.data()))) return rc;
                 if ((rc = combine(w, j + 1, h.data(), -1.0))) return rc;
                 for (int i = 0; i <= j; ++i) Hat(i, j) += h[i];
+                if ((rc = norm(w, &hn))) return rc;
             }
-            double hn = 0.0;
-            if ((rc = norm(w, &hn))) return rc;
             Hat(j + 1, j) = hn;
             if (hn > 0.0)
                 CK(dev::gm_axpby(row(j + 1), make_double2(1.0 / hn, 0.0), w, make_double2(0.0, 0.0),
