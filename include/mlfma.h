@@ -334,7 +334,9 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * parent ranges balanced by record count and parents handed out dynamically.
  * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
  * and l+1, -1 on the leaf level and above level 3): 0 three passes through
- * HBM (ids _S1.._S3), 1 one pass with the intermediates in LDS.
+ * HBM (ids _S1.._S3), 1 + k one pass with the intermediates in LDS in work
+ * split k (children per item, waves per workgroup; 3 splits for the bands
+ * 8 -> 13, 2 for 13 -> 20).
  * kernel = MLFMA_K_P2P (one entry, out[0]; the level argument of
  * mlfma_ops_set_variant is ignored): where the concurrent schedule forks the
  * near field, 1 at the start of the matvec, 0 at the start of the downward

@@ -282,18 +282,18 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
 }
 
 // One-pass interpolation / anterpolation of the level pair (l, l+1).
-hipError_t launch_interp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s)
+hipError_t launch_interp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s, int shape)
 {
     DevLevel &P = o->lev[l], &C = o->lev[l + 1];
-    return dev::interp_fused(P.nbox, R, C.L, P.L, P.child_start, C.oct, C.S, P.iF, P.iA, P.iG,
-                             P.shift_axis, P.S, s);
+    return dev::interp_fused(P.nbox, R, C.L, P.L, shape, P.child_start, C.oct, C.S, P.iF, P.iA,
+                             P.iG, P.shift_axis, P.S, s);
 }
 
-hipError_t launch_anterp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s)
+hipError_t launch_anterp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s, int shape)
 {
     DevLevel &P = o->lev[l], &C = o->lev[l + 1];
-    return dev::anterp_fused(P.nbox, R, C.L, P.L, P.child_start, C.oct, P.Lloc, P.aF, P.aB, P.aG,
-                             P.shift_axis, C.Lloc, s);
+    return dev::anterp_fused(P.nbox, R, C.L, P.L, shape, P.child_start, C.oct, P.Lloc, P.aF,
+                             P.aB, P.aG, P.shift_axis, C.Lloc, s);
 }
 
 // Three-pass interpolation / anterpolation of the level pair (l, l+1).
@@ -374,16 +374,31 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l < o->n_lev && rc == MLFMA_OK; ++l) {
         DevLevel &P = o->lev[l];
         if (!P.onepass_ok || b3) continue;
-        const float ts = time_best(s, e0, e1, [&] { return launch_interp_staged(o, l, R, s); });
-        const float tf = time_best(s, e0, e1, [&] { return launch_interp_onepass(o, l, R, s); });
-        const float as = time_best(s, e0, e1, [&] { return launch_anterp_staged(o, l, R, s); });
-        const float af = time_best(s, e0, e1, [&] { return launch_anterp_onepass(o, l, R, s); });
-        if (ts < 0.f || tf < 0.f || as < 0.f || af < 0.f) {
+        // variant 0: three passes; 1 + k: one pass in work split k
+        float bi = time_best(s, e0, e1, [&] { return launch_interp_staged(o, l, R, s); });
+        float ba = time_best(s, e0, e1, [&] { return launch_anterp_staged(o, l, R, s); });
+        if (bi < 0.f || ba < 0.f) {
             rc = fail(MLFMA_EDEVICE, "autotune: interpolation variants failed on level %d", l);
             break;
         }
-        P.interp_variant = tf < ts ? 1 : 0;
-        P.anterp_variant = af < as ? 1 : 0;
+        P.interp_variant = P.anterp_variant = 0;
+        const int nsh = dev::pair_onepass_shapes(o->lev[l + 1].L, P.L);
+        for (int k = 0; k < nsh && rc == MLFMA_OK; ++k) {
+            const float tf = time_best(s, e0, e1, [&] { return launch_interp_onepass(o, l, R, s, k); });
+            const float af = time_best(s, e0, e1, [&] { return launch_anterp_onepass(o, l, R, s, k); });
+            if (tf < 0.f || af < 0.f) {
+                rc = fail(MLFMA_EDEVICE, "autotune: one-pass variant %d failed on level %d", k, l);
+                break;
+            }
+            if (tf < bi) {
+                bi = tf;
+                P.interp_variant = 1 + k;
+            }
+            if (af < ba) {
+                ba = af;
+                P.anterp_variant = 1 + k;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -423,8 +438,8 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
-        if (P.interp_variant == 1) {
-            LAUNCH(MLFMA_K_INTERP, launch_interp_onepass(o, l, R, s));
+        if (P.interp_variant >= 1) {
+            LAUNCH(MLFMA_K_INTERP, launch_interp_onepass(o, l, R, s, P.interp_variant - 1));
         } else {
             LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s, b3));
             LAUNCH(MLFMA_K_INTERP_S2, dev::theta_map(o->X1, C.nbox * R, C.nth, M, P.iA, P.nth, o->X2, s, b3));
@@ -445,8 +460,8 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     for (int l = 3; l < nl; ++l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
-        if (P.anterp_variant == 1) {
-            LAUNCH(MLFMA_K_ANTERP, launch_anterp_onepass(o, l, R, s));
+        if (P.anterp_variant >= 1) {
+            LAUNCH(MLFMA_K_ANTERP, launch_anterp_onepass(o, l, R, s, P.anterp_variant - 1));
             continue;
         }
         LAUNCH(MLFMA_K_ANTERP_S1, dev::anterp_s1(P.Lloc, C.parent, C.oct, C.nbox, R, P.nth, P.nph, P.shift, P.aF, M,
@@ -1335,8 +1350,10 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)
             return fail(MLFMA_EINVAL, "ops_set_variant: bad level pair %d", level);
-        if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
-        if (variant == 1 && (!o->lev[level].onepass_ok || (o->flags & MLFMA_BF16X3_INTERP)))
+        const int nsh = dev::pair_onepass_shapes(o->lev[level + 1].L, o->lev[level].L);
+        if (variant < 0 || variant > std::max(1, nsh))
+            return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant >= 1 && (!o->lev[level].onepass_ok || (o->flags & MLFMA_BF16X3_INTERP)))
             return fail(MLFMA_EINVAL, "ops_set_variant: one-pass kernel unavailable on level pair %d",
                         level);
         (kernel == MLFMA_K_INTERP ? o->lev[level].interp_variant : o->lev[level].anterp_variant) =

@@ -457,42 +457,63 @@ hipError_t launch_shape(const float2 *In, const int32_t *child_start, const uint
 }
 
 // The instantiated level pairs (the bands of a 0.25-wavelength leaf at 3
-// digits and its parent): children per item and waves per workgroup are
-// chosen for LDS occupancy.
+// digits and its parent), each in several work splits (children per item
+// BW, waves per workgroup NW, resident waves per SIMD MINW) that trade LDS
+// occupancy against MFMA tile fill: one child per item leaves 3/4 of the
+// s2 tiles' columns empty, two children halve that.  The autotuner times
+// them.
+//   (8, 13):  0: BW 1, NW 8;  1: BW 2, NW 4 (two workgroups per CU);
+//             2: BW 1, NW 4 (three workgroups per CU)
+//   (13, 20): 0: BW 1, NW 8;  1: BW 2, NW 4
 template <bool DOWN>
-hipError_t dispatch(int Lc, int Lp, const float2 *In, const int32_t *cs, const uint8_t *oct,
-                    const float *F, const float *Am, const float *G, const float2 *E3,
-                    float2 *Out, int64_t nparent, int R, hipStream_t st)
+hipError_t dispatch(int Lc, int Lp, int shape, const float2 *In, const int32_t *cs,
+                    const uint8_t *oct, const float *F, const float *Am, const float *G,
+                    const float2 *E3, float2 *Out, int64_t nparent, int R, hipStream_t st)
 {
-    if (Lc == 8 && Lp == 13)
+    if (Lc == 8 && Lp == 13) {
+        if (shape == 1)
+            return launch_shape<Shape<8, 13, DOWN, 2, 4, 2>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
+        if (shape == 2)
+            return launch_shape<Shape<8, 13, DOWN, 1, 4, 3>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
         return launch_shape<Shape<8, 13, DOWN, 1, 8, 4>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
-    if (Lc == 13 && Lp == 20)
+    }
+    if (Lc == 13 && Lp == 20) {
+        if (shape == 1)
+            return launch_shape<Shape<13, 20, DOWN, 2, 4, 1>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
         return launch_shape<Shape<13, 20, DOWN, 1, 8, 2>>(In, cs, oct, F, Am, G, E3, Out, nparent, R, st);
+    }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool pair_onepass_fits(int Lc, int Lp)
+bool pair_onepass_fits(int Lc, int Lp) { return pair_onepass_shapes(Lc, Lp) > 0; }
+
+int pair_onepass_shapes(int Lc, int Lp)
 {
-    return (Lc == 8 && Lp == 13) || (Lc == 13 && Lp == 20);
+    if (Lc == 8 && Lp == 13) return 3;
+    if (Lc == 13 && Lp == 20) return 2;
+    return 0;
 }
 
-hipError_t interp_fused(int64_t nboxp, int R, int Lc, int Lp, const int32_t *child_start,
-                        const uint8_t *child_oct, const float2 *Sc, const float *F, const float *A,
-                        const float *G, const float2 *E3, float2 *Sp, hipStream_t s)
+hipError_t interp_fused(int64_t nboxp, int R, int Lc, int Lp, int shape,
+                        const int32_t *child_start, const uint8_t *child_oct, const float2 *Sc,
+                        const float *F, const float *A, const float *G, const float2 *E3,
+                        float2 *Sp, hipStream_t s)
 {
     if (nboxp == 0) return hipSuccess;
-    return dispatch<false>(Lc, Lp, Sc, child_start, child_oct, F, A, G, E3, Sp, nboxp, R, s);
+    return dispatch<false>(Lc, Lp, shape, Sc, child_start, child_oct, F, A, G, E3, Sp, nboxp, R,
+                           s);
 }
 
-hipError_t anterp_fused(int64_t nboxp, int R, int Lc, int Lp, const int32_t *child_start,
-                        const uint8_t *child_oct, const float2 *Lpar, const float *F,
-                        const float *B, const float *G, const float2 *E3, float2 *Lch,
-                        hipStream_t s)
+hipError_t anterp_fused(int64_t nboxp, int R, int Lc, int Lp, int shape,
+                        const int32_t *child_start, const uint8_t *child_oct, const float2 *Lpar,
+                        const float *F, const float *B, const float *G, const float2 *E3,
+                        float2 *Lch, hipStream_t s)
 {
     if (nboxp == 0) return hipSuccess;
-    return dispatch<true>(Lc, Lp, Lpar, child_start, child_oct, F, B, G, E3, Lch, nboxp, R, s);
+    return dispatch<true>(Lc, Lp, shape, Lpar, child_start, child_oct, F, B, G, E3, Lch, nboxp,
+                          R, s);
 }
 
 }  // namespace dev

@@ -64,14 +64,17 @@ hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
 // L2L: Lch[c][r] += anterp(conj(shift[oct c]) (.) Lpar[parent c][r])
 // F [nphi_in][M], A [(M+1)/2][ntheta_in][ntheta_out], G [M][nphi_out];
 // E3: the axis factors of the shift on the parent grid.
+// shape: the work split, 0 .. pair_onepass_shapes(Lc, Lp) - 1.
 bool pair_onepass_fits(int Lc, int Lp);
-hipError_t interp_fused(int64_t nboxp, int R, int Lc, int Lp, const int32_t *child_start,
-                        const uint8_t *child_oct, const float2 *Sc, const float *F, const float *A,
-                        const float *G, const float2 *E3, float2 *Sp, hipStream_t s);
-hipError_t anterp_fused(int64_t nboxp, int R, int Lc, int Lp, const int32_t *child_start,
-                        const uint8_t *child_oct, const float2 *Lpar, const float *F,
-                        const float *B, const float *G, const float2 *E3, float2 *Lch,
-                        hipStream_t s);
+int pair_onepass_shapes(int Lc, int Lp);
+hipError_t interp_fused(int64_t nboxp, int R, int Lc, int Lp, int shape,
+                        const int32_t *child_start, const uint8_t *child_oct, const float2 *Sc,
+                        const float *F, const float *A, const float *G, const float2 *E3,
+                        float2 *Sp, hipStream_t s);
+hipError_t anterp_fused(int64_t nboxp, int R, int Lc, int Lp, int shape,
+                        const int32_t *child_start, const uint8_t *child_oct, const float2 *Lpar,
+                        const float *F, const float *B, const float *G, const float2 *E3,
+                        float2 *Lch, hipStream_t s);
 
 // out[i][a] = sum_r Re[conj(g[i][r]) Fq[i][r][a] + q[i][r] Fg[i][r][a]]
 // (q, g caller order, dtype 0 = complex64 / 1 = complex128; out float/double)

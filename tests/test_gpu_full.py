@@ -48,3 +48,38 @@ def test_full_sphere262k_r64_bf16x3():
 
 def test_full_cube1m_r16():
     assert _run_full("cube1m_r16", 96) < 1e-3
+
+
+def test_onepass_work_splits_agree_sphere262k():
+    """Every one-pass work split of the two lowest level pairs (bands 8 -> 13
+    and 13 -> 20) gives the three-pass result of the 262k sphere at 4 RHS
+    (FP32 reassociation only), and one of them matches the dense definition
+    on sampled targets."""
+    torch = cuda_or_skip()
+    from oracle import dense
+    from paper_2006_15367_amd import mlfma as G
+    xyz, q = W.make("sphere262k", nrhs=4)
+    say("full: one-pass work splits, sphere262k, 4 RHS")
+    tree = G.Tree(xyz, W.LEAF_SIZE)
+    ops = G.Operators(tree, K, W.DIGITS, max_rhs=4, autotune=False)
+    nl = tree.info()["n_levels"]
+    qd = torch.from_numpy(q.astype(np.complex64)).cuda()
+    pairs = {nl - 1: 3, nl - 2: 2}  # level of the pair -> number of splits
+    for k in ("interp", "anterp"):
+        for l in range(3, nl):
+            ops.set_variant(l, 0, kernel=k)
+    ref = ops.matvec(qd).cpu().numpy()
+    for v in (1, 2, 3):
+        for k in ("interp", "anterp"):
+            for l, nsh in pairs.items():
+                ops.set_variant(l, min(v, nsh), kernel=k)
+        say("one-pass variant", v)
+        got = ops.matvec(qd).cpu().numpy()
+        torch.cuda.synchronize()
+        err = rel_l2(got, ref)
+        say("variant", v, "rel L2 vs three passes", err)
+        assert err < 1e-5, (v, err)
+    rng = np.random.default_rng(52)
+    idx = rng.choice(xyz.shape[0], 128, replace=False)
+    dref = dense.potential(xyz, q[:, 1], K, tgt=xyz[idx])
+    assert rel_l2(got[idx, 1], dref) < 1e-3
