@@ -329,7 +329,8 @@ def main():
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
         "m2l_variant_per_level": ops.variants("m2l"),
-        "near_field_forked_at_start": ops.variants("p2p")[0],
+        "near_field_fork": {0: "downward pass", 1: "start", 2: "after C2M"}.get(
+            ops.variants("p2p")[0], "one stream"),
         "onepass_interp_per_level": ops.variants("interp"),
         "onepass_anterp_per_level": ops.variants("anterp"),
         "roofline": rl,

@@ -339,8 +339,8 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * 8 -> 13, 2 for 13 -> 20).
  * kernel = MLFMA_K_P2P (one entry, out[0]; the level argument of
  * mlfma_ops_set_variant is ignored): where the concurrent schedule forks the
- * near field, 1 at the start of the matvec, 0 at the start of the downward
- * pass, -1 when every kernel runs on the caller's stream.
+ * near field, 1 at the start of the matvec, 2 after C2M, 0 at the start of
+ * the downward pass, -1 when every kernel runs on the caller's stream.
  */
 int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
 /* Diagnostics: force a variant of `kernel` on `level` (3..n_levels; for the

@@ -82,7 +82,9 @@ struct mlfma_ops_s {
     // library streams for the concurrent schedule (near field; M2L) and
     // the events that fork and join them
     hipStream_t side[2] = {nullptr, nullptr};
-    bool near_early = false;         // concurrent: near field forked at the start
+    // concurrent: where the near field forks: 0 start of the downward pass,
+    // 1 start of the matvec, 2 after C2M
+    int near_fork = 0;
     // GMRES workspace: Krylov basis [(gm_cap + 1) x n], work vector,
     // dot-product partials, coefficient vector (allocated on first solve)
     int gm_cap = 0;
@@ -414,26 +416,34 @@ int autotune(mlfma_ops_s *o)
 template <class Near>
 int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
 {
+    const int fork = conc ? o->near_fork : 1;
     const int nl = o->n_lev;
     DevLevel &leaf = o->lev[nl];
     const float kw = (float)o->k;
     const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
     hipStream_t sm = conc ? o->side[1] : s;
     auto m2l_level = [&](int l) -> int {
-        if (conc) {
+        // level 3, the last, stays on the caller's stream: the downward
+        // pass waits for it anyway, and a fork and join around it cost
+        // more than the overlap gains
+        const bool side = conc && l > 3;
+        if (side) {
             CK(hipEventRecord(o->ev_S[l], s));
             CK(hipStreamWaitEvent(sm, o->ev_S[l], 0));
         }
-        hipStream_t s = sm;
+        hipStream_t s0 = s;
+        hipStream_t s = side ? sm : s0;
         DevLevel &D = o->lev[l];
         // concurrent: the record variants leave a quarter of the CUs (their
         // workgroups hold a CU's whole LDS) to the upward chain, the
         // critical path, which otherwise waits for M2L workgroups to retire
-        const int cap = conc ? dev::cu_count() - dev::cu_count() / 4 : 0;
+        const int cap = side ? dev::cu_count() - dev::cu_count() / 4 : 0;
         LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s, cap));
         return MLFMA_OK;
     };
     LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
+    if (fork == 2)
+        if (int r = near()) return r;
     if (int r = m2l_level(nl)) return r;
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
@@ -448,10 +458,10 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
         }
         if (int r = m2l_level(l)) return r;
     }
-    // the near field joins here: it fills the device during the downward
+    // the near field forked here fills the device during the downward
     // pass, whose small kernels leave most CUs idle (forked at the start,
-    // it took CUs from C2M and the upward chain)
-    if (conc)
+    // it takes CUs from C2M and the upward chain)
+    if (fork == 0)
         if (int r = near()) return r;
     if (conc) {
         CK(hipEventRecord(o->ev_m2l, sm));
@@ -475,8 +485,9 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
 // The near field and the far field from the gathered charges o->qs up to
 // the leaf locals and o->near.  Concurrent schedule (side streams present,
 // not disabled): the near field runs on side[0], forked at the start
-// (o->near_early) or at the start of the downward pass, and joined on `s`
-// at the end; the M2L of each level runs on side[1].
+// (o->near_fork 1), after C2M (2) or at the start of the downward pass (0),
+// and joined on `s` at the end; the M2L of each level but the last (level
+// 3) runs on side[1].
 int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
 {
     const bool far = (parts & MLFMA_FAR) && o->n_lev >= 3;
@@ -501,7 +512,7 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
         return MLFMA_OK;
     };
     auto none = []() -> int { return MLFMA_OK; };
-    const bool early = !conc || o->near_early;
+    const bool early = !conc || o->near_fork == 1;
     if (early)
         if (int r = near()) return r;
     if (far) {
@@ -513,7 +524,8 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
 }
 
 // Pick where the concurrent schedule forks the near field: time the core
-// (near + far field, max_rhs right-hand sides) both ways on a scratch stream.
+// (near + far field, max_rhs right-hand sides) for each fork point on a
+// scratch stream.
 int tune_schedule(mlfma_ops_s *o)
 {
     if (!o->side[0] || o->n_lev < 3) return MLFMA_OK;
@@ -524,10 +536,10 @@ int tune_schedule(mlfma_ops_s *o)
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     float best = 1e30f;
-    bool best_early = false;
+    int best_fork = 0;
     int rc = MLFMA_OK;
-    for (int mode = 0; mode < 2 && rc == MLFMA_OK; ++mode) {
-        o->near_early = mode == 1;
+    for (int mode = 0; mode < 3 && rc == MLFMA_OK; ++mode) {
+        o->near_fork = mode;
         rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
         float t = 0.f;
         if (rc == MLFMA_OK && hipEventRecord(e0, s) == hipSuccess) {
@@ -537,11 +549,11 @@ int tune_schedule(mlfma_ops_s *o)
                 hipEventSynchronize(e1) == hipSuccess &&
                 hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best) {
                 best = t;
-                best_early = o->near_early;
+                best_fork = mode;
             }
         }
     }
-    o->near_early = best_early;
+    o->near_fork = best_fork;
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1334,7 +1346,7 @@ int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
         return MLFMA_OK;
     }
     if (kernel == MLFMA_K_P2P) {
-        if (max_entries >= 1) out[0] = o->side[0] ? (o->near_early ? 1 : 0) : -1;
+        if (max_entries >= 1) out[0] = o->side[0] ? o->near_fork : -1;
         return MLFMA_OK;
     }
     return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
@@ -1359,9 +1371,9 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
         (kernel == MLFMA_K_INTERP ? o->lev[level].interp_variant : o->lev[level].anterp_variant) =
             variant;
     } else if (kernel == MLFMA_K_P2P) {
-        if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant < 0 || variant > 2) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         if (!o->side[0]) return fail(MLFMA_EINVAL, "ops_set_variant: one-stream handle has no schedule");
-        o->near_early = variant == 1;
+        o->near_fork = variant;
     } else {
         return fail(MLFMA_EINVAL, "ops_set_variant: kernel %d has no variants", kernel);
     }

@@ -340,7 +340,8 @@ class Operators:
     def variants(self, kernel="m2l"):
         """Per-level kernel variant chosen by the autotuner (-1: no kernel).
         kernel="p2p": one entry, where the concurrent schedule forks the near
-        field (1 at the start, 0 at the downward pass, -1 one stream)."""
+        field (1 at the start, 2 after C2M, 0 at the downward pass, -1 one
+        stream)."""
         nl = self.tree.info()["n_levels"]
         out = np.full(max(nl, 1), -1, np.int32)
         _check(_load().mlfma_ops_variants(self._h, KERNELS.index(kernel), out.ctypes.data,
