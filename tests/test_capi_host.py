@@ -136,3 +136,25 @@ def test_status_strings():
     lib = G._load()
     for s in range(6):
         assert lib.mlfma_status_string(s).startswith(b"MLFMA_")
+
+
+def test_solve_gmres_argument_errors():
+    """mlfma_solve_gmres rejects bad arguments before it touches a device,
+    with the outputs cleared."""
+    lib = G._load()
+    it = ctypes.c_int(7)
+    rr = ctypes.c_double(3.0)
+    bad = [
+        (1j, 0, 10, 1e-5),           # restart < 1
+        (1j, 501, 10, 1e-5),         # restart > 500
+        (1j, 30, -1, 1e-5),          # max_iters < 0
+        (1j, 30, 10, 0.0),           # tol <= 0
+        (1j, 30, 10, float("nan")),  # tol not finite
+        (complex(float("inf"), 0), 30, 10, 1e-5),  # shift not finite
+        (1j, 30, 10, 1e-5),          # null handle
+    ]
+    for sh, restart, maxit, tol in bad:
+        st = lib.mlfma_solve_gmres(None, None, None, sh.real, sh.imag, restart, maxit, tol,
+                                   ctypes.byref(it), ctypes.byref(rr), None)
+        assert st == G.EINVAL, (sh, restart, maxit, tol)
+        assert it.value == 0 and rr.value == 0.0
