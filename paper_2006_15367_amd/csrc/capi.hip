@@ -564,7 +564,7 @@ int tune_schedule(mlfma_ops_s *o)
 // conj_in/conj_out: -1 = follow MLFMA_CONJ in parts
 int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
               uint32_t parts, int field, hipStream_t s, int conj_in = -1, int conj_out = -1,
-              int out_dtype = -1)
+              int out_dtype = -1, bool allow_graph = true)
 {
     if (!o) return fail(MLFMA_EINVAL, "matvec: ops handle is NULL");
     if (nrhs < 1 || nrhs > o->max_rhs)
@@ -604,8 +604,8 @@ int do_matvec(mlfma_ops_s *o, const void *q, void *out, int64_t nrhs, int dtype,
                                              o->near, o->n, R, field, far ? 1 : 0, cout, odt, out, s));
         return MLFMA_OK;
     };
-    const bool graph = rc == MLFMA_OK && (o->flags & MLFMA_USE_GRAPH) && s != nullptr &&
-                       o->prof_mask == 0;
+    const bool graph = rc == MLFMA_OK && allow_graph && (o->flags & MLFMA_USE_GRAPH) &&
+                       s != nullptr && o->prof_mask == 0;
     if (rc == MLFMA_OK && !graph) rc = enqueue();
     if (rc == MLFMA_OK && graph) {
         mlfma_ops_s::GraphEntry *hit = nullptr;
@@ -1106,7 +1106,11 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
     };
     // y <- (shift I + A) v
     auto op = [&](const float2 *v, float2 *y) -> int {
-        if (int r = do_matvec(o, v, y, 1, MLFMA_C64, MLFMA_NEAR | MLFMA_FAR, 0, s)) return r;
+        // eager: the solver's operands cycle through the basis rows, more
+        // buffer pairs than the graph cache holds
+        if (int r = do_matvec(o, v, y, 1, MLFMA_C64, MLFMA_NEAR | MLFMA_FAR, 0, s, -1, -1, -1,
+                              false))
+            return r;
         CK(dev::gm_axpby(y, make_double2(shift_re, shift_im), v, make_double2(1.0, 0.0), n, s));
         return MLFMA_OK;
     };

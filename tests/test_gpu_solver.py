@@ -69,3 +69,22 @@ def test_gmres_iteration_budget_and_initial_guess(case):
     _, x2, it2, rr2 = _solve(case, restart=30, max_iters=200, tol=1e-5, x0=x)
     assert it2 == 0 and rr2 == pytest.approx(rr, abs=1e-7)
     assert torch.equal(x2, x)
+
+
+def test_gmres_on_a_graph_handle_equals_eager(case):
+    """A handle made with graph=True solves with eager matvecs (its basis
+    rows are more operand pairs than the graph cache holds): same steps,
+    same solution as the plain handle."""
+    torch = case["torch"]
+    G = case["G"]
+    say("gmres: graph handle")
+    tree = G.Tree(case["xyz"], W.LEAF_SIZE)
+    gops = G.Operators(tree, K, W.DIGITS, graph=True)
+    st = torch.cuda.Stream()
+    bd = torch.from_numpy(case["b"].astype(np.complex64)).cuda()
+    with torch.cuda.stream(st):
+        xg, itg, rrg = gops.solve(bd, SHIFT, restart=30, max_iters=200, tol=1e-5, stream=st)
+    st.synchronize()
+    _, x, it, rr = _solve(case, restart=30, max_iters=200, tol=1e-5)
+    assert itg == it and rrg == pytest.approx(rr, rel=1e-6)
+    assert rel_l2(xg.cpu().numpy(), x.cpu().numpy()) < 1e-6
