@@ -87,12 +87,15 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
     const int b = it.x;
     const int p0 = pt_start[b];
     const int nt = min(64, pt_start[b + 1] - p0 - it.y);
-    int Tp = 1;
-    while (Tp < nt) Tp <<= 1;
-    const int G = NT / Tp;
-    const int t = tid & (Tp - 1), g = tid / Tp;
-    const bool tv = t < nt;
-    const int i = p0 + it.y + (tv ? t : 0);
+    // lanes: target t = lane % nt, source group lane / nt of GW = 64 / nt
+    // groups per wave (lanes past GW nt idle); G groups in all
+    const int GW = 64 / nt;
+    const int G = NW * GW;
+    const int lane_ = tid & 63;
+    const int t = lane_ % nt;
+    const bool active = lane_ < GW * nt;
+    const int g = (tid >> 6) * GW + lane_ / nt;
+    const int i = p0 + it.y + t;
     const int r0 = blockIdx.y * RC;
     const int rc = min(RC, R - r0);
     const float4 pi = pts[i];
@@ -105,7 +108,7 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
 
     auto process = [&](int n) {
         __syncthreads();
-        for (int x = g; x < n; x += G) {
+        for (int x = active ? g : n; x < n; x += G) {
             const float4 sj = sp[x];
             const float dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -207,47 +210,31 @@ k_p2p(const int2 *__restrict__ items, const float4 *__restrict__ pts,
         }
         process(n);
     }
-    // add the G partial sums of each target: lanes t, t+T, ... inside a wave
-    // by shuffles, then the waves through LDS
-    const int GW = Tp < 64 ? 64 / Tp : 1;  // groups per wave
-    for (int sft = Tp; sft < 64; sft <<= 1) {
+    // add the partial sums of each target: lanes t + k nt of every wave,
+    // through LDS; lane t < nt of wave 0 then holds the total of target t
+    __shared__ float2 red[NW * 64 * RC * NA];  // [NW][64][RC][NA]
+    {
+        const int wv = tid >> 6;
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) red[((wv * 64 + lane_) * RC + c) * NA + a] = acc[c][a];
+    }
+    __syncthreads();
+    if (tid < nt) {
 #pragma unroll
         for (int c = 0; c < RC; ++c)
 #pragma unroll
             for (int a = 0; a < NA; ++a) {
-                acc[c][a].x += __shfl_xor(acc[c][a].x, sft, 64);
-                acc[c][a].y += __shfl_xor(acc[c][a].y, sft, 64);
-            }
-    }
-    (void)GW;
-    if (NW > 1) {
-        // after the shuffles, lane t (< Tp, < 64) of every wave holds that
-        // wave's sum for target t (Tp <= 64); with Tp = 64 each wave holds
-        // one group's sum per lane
-        __shared__ float2 red[NW * 64 * RC * NA];  // [NW][64][RC][NA]
-        const int wv = tid >> 6, ln = tid & 63;
-#pragma unroll
-        for (int c = 0; c < RC; ++c)
-#pragma unroll
-            for (int a = 0; a < NA; ++a) red[((wv * 64 + ln) * RC + c) * NA + a] = acc[c][a];
-        __syncthreads();
-        if (wv == 0) {
-#pragma unroll
-            for (int c = 0; c < RC; ++c)
-#pragma unroll
-                for (int a = 0; a < NA; ++a) {
-                    float2 v = red[(ln * RC + c) * NA + a];
-                    for (int w = 1; w < NW; ++w) {
-                        const float2 u = red[((w * 64 + ln) * RC + c) * NA + a];
+                float2 v = make_float2(0.f, 0.f);
+                for (int w = 0; w < NW; ++w)
+                    for (int k = 0; k < GW; ++k) {
+                        const float2 u = red[((w * 64 + t + k * nt) * RC + c) * NA + a];
                         v.x += u.x;
                         v.y += u.y;
                     }
-                    acc[c][a] = v;
-                }
-        }
-    }
-    // lane t < Tp of wave 0 now holds the total of target t
-    if (tid < Tp && tv) {
+                acc[c][a] = v;
+            }
 #pragma unroll
         for (int c = 0; c < RC; ++c)
             if (c < rc)
