@@ -96,3 +96,15 @@ def test_gmres_on_a_graph_handle_equals_eager(case):
     _, x, it, rr = _solve(case, restart=30, max_iters=200, tol=1e-5)
     assert abs(itg - it) <= 1 and rrg <= 1e-5
     assert rel_l2(xg.cpu().numpy(), x.cpu().numpy()) < 1e-5
+
+
+def test_gmres_zero_right_hand_side(case):
+    """b = 0 gives x = 0 with no operator application, whatever x0 was."""
+    torch = case["torch"]
+    say("gmres: b = 0")
+    zb = torch.zeros(case["b"].shape[0], dtype=torch.complex64, device="cuda")
+    x0 = torch.ones_like(zb)
+    x, it, rr = case["ops"].solve(zb, SHIFT, restart=10, max_iters=50, tol=1e-5, x0=x0)
+    torch.cuda.synchronize()
+    assert it == 0 and rr == 0.0
+    assert float(torch.linalg.vector_norm(x)) == 0.0
