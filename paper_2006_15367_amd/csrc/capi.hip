@@ -275,9 +275,9 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
     case 3:
     case 4:
     case 5:
+    case 6:
         return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
-                            D.rec_off, D.T, D.S, R, D.Lloc, s,
-                            variant == 3 ? 0 : variant == 4 ? 1 : 2, max_wg);
+                            D.rec_off, D.T, D.S, R, D.Lloc, s, variant - 3, max_wg);
     default:
         return dev::m2l(D.nbox, D.K, D.far_start, D.far_src, D.far_type, D.T, D.S, R, D.Lloc, s);
     }
@@ -359,7 +359,8 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < 6; ++v) {
+        for (int v = 0; v < 7; ++v) {
+            if (v == 6 && R != 1) continue;  // the 32-sample kernel serves one RHS
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -1361,7 +1362,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-        if (variant < 0 || variant > 5) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant < 0 || variant > 6) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         o->lev[level].m2l_variant = variant;
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)

@@ -94,7 +94,9 @@ hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start,
 int cu_count();
 
 // schedule: 0 contiguous parent ranges, 1 the slice-major sweep for many
-// right-hand sides, 2 ranges balanced by record count with dynamic parents;
+// right-hand sides, 2 ranges balanced by record count with dynamic parents,
+// 3 the same with a 32-sample slice and half-waves on record pairs (one RHS;
+// several RHS take 2);
 // max_wg caps the resident workgroups (0: the CU count)
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,

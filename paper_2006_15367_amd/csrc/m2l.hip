@@ -579,6 +579,134 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
     }
 }
 
+// One right-hand side with a 32-sample operator slice: (316 + 1) x 32 x 8 B
+// of LDS, so two workgroups share a CU and twice the waves hide latency.
+// The two half-waves take the even and the odd records of the parent on
+// the same 32 samples (lane k and k + 32 hold partial sums of one sample,
+// added by a lane swap at the end); records are walked in batches of two
+// pairs, the next batch's loads issued before the current batch computes.
+// Record offsets address 64-sample rows and are halved here.
+template <int NO>
+__device__ __forceinline__ void m2l_rec_parent_half(const char *Tsb, int lane8, int half, int e0,
+                                                    int e1, const int32_t *__restrict__ rec_src,
+                                                    const int32_t *__restrict__ rec_off,
+                                                    const float2 *__restrict__ S, int64_t K,
+                                                    int64_t kk, float2 (&acc)[8])
+{
+    constexpr int U = 2;  // record pairs per batch (lists are padded to 4)
+    const int nb = (e1 - e0) / (2 * U);
+    if (nb <= 0) return;
+    float2 va[U], vb[U];
+    int oa[U][NO], ob[U][NO];
+    auto fetch = [&](int j, float2 (&v)[U], int (&of)[U][NO]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + 2 * (j * U + u);
+            const int s0 = rec_src[e], s1 = rec_src[e + 1];
+            const int src = half ? s1 : s0;
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                const int f0 = rec_off[8 * e + i] >> 1, f1 = rec_off[8 * (e + 1) + i] >> 1;
+                of[u][i] = half ? f1 : f0;
+            }
+            v[u] = S[(int64_t)src * K + kk];
+        }
+    };
+    auto compute = [&](const float2 (&v)[U], const int (&of)[U][NO]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                const float2 tv = *(const float2 *)(Tsb + (of[u][i] + lane8));
+                acc[i] = cfma(tv, v[u], acc[i]);
+            }
+    };
+    fetch(0, va, oa);
+    for (int j = 0;;) {
+        fetch(j + 1, vb, ob);
+        compute(va, oa);
+        if (++j >= nb) break;
+        fetch(j + 1, va, oa);
+        compute(vb, ob);
+        if (++j >= nb) break;
+    }
+}
+
+template <int NW>
+__global__ void __launch_bounds__(64 * NW, 8)  // two workgroups: 8 waves per SIMD
+k_m2l_rec_half(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ child_start,
+               const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
+               const int32_t *__restrict__ rec_off, const float2 *__restrict__ T,
+               const float2 *__restrict__ S, int nkc, int nrange, float2 *__restrict__ Lout)
+{
+    // the balanced schedule of k_m2l_rec (record-balanced XCD-contiguous
+    // parent ranges, parents handed to waves from an LDS counter)
+    extern __shared__ float2 Ts[];  // [ntypes + 1][32], row ntypes = 0
+    __shared__ int next_parent;
+    const int64_t w = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int kc = (int)(w % nkc);
+    const int64_t k0 = (int64_t)kc * 32;
+    stage_t_slice<32>(Ts, T, ntypes, K, k0);
+    for (int idx = threadIdx.x; idx < 32; idx += blockDim.x)
+        Ts[ntypes * 32 + idx] = make_float2(0.f, 0.f);
+    if (threadIdx.x == 0) next_parent = 0;
+    __syncthreads();
+    const char *Tsb = (const char *)Ts;
+    const int lane = threadIdx.x & 63;
+    const int kl = lane & 31, half = lane >> 5;
+    const int lane8 = kl * 8;
+    const int64_t k = k0 + kl;
+    const bool valid = k < K;
+    const int64_t kk = valid ? k : K - 1;
+    const int64_t total = rec_start[nparent];
+    const int64_t rg = w / nkc;
+    auto lower = [&](int64_t target) -> int64_t {
+        int64_t lo = 0, hi = nparent;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)__builtin_amdgcn_readfirstlane(rec_start[mid]) < target) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int64_t pbeg = rg == 0 ? 0 : lower(total * rg / nrange);
+    const int64_t pend = rg == nrange - 1 ? nparent : lower(total * (rg + 1) / nrange);
+    auto take = [&]() -> int64_t {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&next_parent, 1);
+        return pbeg + __builtin_amdgcn_readfirstlane(t);
+    };
+    for (int64_t P = take(); P < pend; P = take()) {
+        const int o0 = __builtin_amdgcn_readfirstlane(child_start[P]);
+        const int no = __builtin_amdgcn_readfirstlane(child_start[P + 1]) - o0;
+        const int e0 = __builtin_amdgcn_readfirstlane(rec_start[P]);
+        const int e1 = __builtin_amdgcn_readfirstlane(rec_start[P + 1]);
+        float2 acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = make_float2(0.f, 0.f);
+        switch (no) {
+#define REC_HALF_CASE(N)                                                                      \
+    case N:                                                                                   \
+        m2l_rec_parent_half<N>(Tsb, lane8, half, e0, e1, rec_src, rec_off, S, K, kk, acc);    \
+        break;
+            REC_HALF_CASE(1) REC_HALF_CASE(2) REC_HALF_CASE(3) REC_HALF_CASE(4)
+            REC_HALF_CASE(5) REC_HALF_CASE(6) REC_HALF_CASE(7) REC_HALF_CASE(8)
+#undef REC_HALF_CASE
+        default: break;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            acc[i].x += __shfl_xor(acc[i].x, 32, 64);
+            acc[i].y += __shfl_xor(acc[i].y, 32, 64);
+        }
+        if (valid && half == 0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (i < no) Lout[(int64_t)(o0 + i) * K + k] = acc[i];
+        }
+    }
+}
+
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
@@ -586,6 +714,20 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
 {
     const bool sweep = schedule == 1;
     if (nparent == 0 || K == 0) return hipSuccess;
+    if (schedule == 3 && R == 1) {
+        // one RHS, 32-sample slice, two workgroups per CU
+        const size_t lds2 = (size_t)(ntypes + 1) * 32 * sizeof(float2);
+        if (2 * (lds2 + 16) > 163840) return hipErrorInvalidValue;
+        const int NW = 16;
+        const int nkc2 = (int)((K + 31) / 32);
+        const int slots = 2 * (max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count());
+        const int nr = (int)std::max<int64_t>(1, std::min<int64_t>(slots / nkc2, (nparent + NW - 1) / NW));
+        hipLaunchKernelGGL((k_m2l_rec_half<16>), dim3((unsigned)(nkc2 * nr)), dim3(64 * NW), lds2, s,
+                           nparent, K, ntypes, child_start, rec_start, rec_src, rec_off, T, S,
+                           nkc2, nr, Lout);
+        return hipGetLastError();
+    }
+    if (schedule == 3) schedule = 2;  // several RHS: the 64-sample balanced schedule
     const size_t lds = (size_t)(ntypes + 1) * 64 * sizeof(float2);
     if (lds + 16 > 163840) return hipErrorInvalidValue;  // + the static counter
     // 32-bit lane offsets (and buffer range) within one source's spectra

@@ -142,7 +142,7 @@ def test_field_vs_dense(c1):
     assert e < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_every_m2l_variant(c1, variant):
     torch = c1["torch"]
     say("c1: M2L variant", variant)
