@@ -332,8 +332,10 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * LDS, 2 sibling groups, 3 sibling groups with per-source records, 4 the
  * same with a slice-major sweep (for many right-hand sides), 5 the same with
  * parent ranges balanced by record count and parents handed out dynamically,
- * 6 as 5 with a 32-sample operator slice (two workgroups per CU; one RHS,
- * calls with several RHS run 5).
+ * 6 as 5 with a 32-sample operator slice (two workgroups per CU), 7 as 5
+ * on antipodal slices (T_{-d}(k) = T_d(-k): the operators of one offset of
+ * each +-pair in LDS, two workgroups per CU); 6 and 7 serve one RHS, calls
+ * with several RHS run 5.
  * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
  * and l+1, -1 on the leaf level and above level 3): 0 three passes through
  * HBM (ids _S1.._S3), 1 + k one pass with the intermediates in LDS in work

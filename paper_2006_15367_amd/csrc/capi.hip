@@ -45,6 +45,13 @@ struct DevLevel {
                                      // the slice-major sweep
     int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
+    // antipodal slices (one-RHS variant 7): operators of one offset of each
+    // +-pair in slice-lane order [ntp][Kp], slice lane -> sample [Kp], and
+    // the record slots as pair * 512 | (negated ? 504 : 0)
+    float2 *Tp = nullptr;
+    int32_t *aperm = nullptr, *rec_off_anti = nullptr;
+    int ntp = 0;
+    int64_t Kp = 0;
     float2 *S = nullptr, *Lloc = nullptr;  // [nbox][R][K]
     int Lc = 0, Mc = 0;
     float2 *shift = nullptr, *shift_axis = nullptr;
@@ -272,6 +279,12 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
     case 2:
         return dev::m2l_sg(Pl.nbox, D.K, D.ntypes, Pl.child_start, Pl.nbr_start, Pl.nbr_idx,
                            D.base, D.typemap, D.T, D.S, R, D.Lloc, s);
+    case 7:
+        if (R == 1)
+            return dev::m2l_anti(Pl.nbox, D.K, D.ntp, Pl.child_start, D.rec_start, D.rec_src,
+                                 D.rec_off_anti, D.Tp, D.aperm, D.Kp, D.S, D.Lloc, s, max_wg);
+        return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
+                            D.rec_off, D.T, D.S, R, D.Lloc, s, 2, max_wg);
     case 3:
     case 4:
     case 5:
@@ -359,8 +372,8 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < 7; ++v) {
-            if (v == 6 && R != 1) continue;  // the 32-sample kernel serves one RHS
+        for (int v = 0; v < 8; ++v) {
+            if (v >= 6 && R != 1) continue;  // variants 6 and 7 serve one RHS
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -743,6 +756,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             pl.add((H.nbox + 1) * 4);
             pl.add(H.nbox * 4 + 343 * 2 + (H.nbox + 1) * 4 + 26 * H.nbox * 4);
             pl.add((int64_t)H.far_src.size() * 36 + (H.nbox + 1) * 4);  // M2L records (bound)
+            pl.add((int64_t)H.far_src.size() * 32);                     // antipodal record slots
+            pl.add(((int64_t)T.ntypes + 1) * (T.K / 2 + 64) * 8 + (T.K + 64) * 4);  // Tp, aperm
             pl.add(H.nbox * R * T.K * 8 * 2);
             if (l < nl) {
                 const LevelTables &C = o->tab[l + 1];
@@ -897,6 +912,64 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 if ((r = upload(o, &D.rec_start, rs.data(), (int64_t)rs.size()))) return r;
                 if ((r = upload(o, &D.rec_src, rsrc.data(), (int64_t)rsrc.size()))) return r;
                 if ((r = upload(o, &D.rec_off, roff.data(), (int64_t)roff.size()))) return r;
+                // antipodal slices: the opposite of sample (i, j) is
+                // (nth - 1 - i, j + nph / 2); T_{-d}(k) = T_d(-k)
+                const int64_t K = T.K;
+                auto anti = [&](int64_t q) -> int64_t {
+                    const int64_t i = q / T.nph, j = q % T.nph;
+                    return (T.nth - 1 - i) * T.nph + (j + T.nph / 2) % T.nph;
+                };
+                std::vector<int64_t> canon;
+                for (int64_t q = 0; q < K; ++q)
+                    if (q < anti(q)) canon.push_back(q);
+                const int64_t npair = (int64_t)canon.size();
+                const int64_t nsl = (npair + 31) / 32;
+                D.Kp = nsl * 64;
+                std::vector<int32_t> ap((size_t)D.Kp, -1);
+                for (int64_t sl = 0; sl < nsl; ++sl)
+                    for (int ln = 0; ln < 32; ++ln) {
+                        const int64_t pr = sl * 32 + ln;
+                        if (pr >= npair) break;
+                        ap[(size_t)(sl * 64 + ln)] = (int32_t)canon[(size_t)pr];
+                        ap[(size_t)(sl * 64 + 63 - ln)] = (int32_t)anti(canon[(size_t)pr]);
+                    }
+                // offset pairs: code(-d) = 342 - code(d); the smaller code
+                // of a used pair names it
+                std::vector<int> tp_of(343, -1), type_code(T.ntypes, -1);
+                int ntp = 0;
+                for (int c = 0; c < 343; ++c) {
+                    if (T.code_to_type[c] < 0) continue;
+                    type_code[T.code_to_type[c]] = c;
+                    const int c0 = std::min(c, 342 - c);
+                    if (tp_of[c0] < 0) tp_of[c0] = ntp++;
+                }
+                D.ntp = ntp;
+                std::vector<float2> tpv((size_t)ntp * D.Kp, make_float2(0.f, 0.f));
+                const float2 *Th = (const float2 *)T.T.data();
+                for (int c0 = 0; c0 < 343; ++c0) {
+                    if (tp_of[c0] < 0) continue;
+                    // the row of offset c0, or the mirrored row of -c0
+                    const bool direct = T.code_to_type[c0] >= 0;
+                    const int t = direct ? T.code_to_type[c0] : T.code_to_type[342 - c0];
+                    for (int64_t e = 0; e < D.Kp; ++e) {
+                        const int32_t q = ap[(size_t)e];
+                        if (q < 0) continue;
+                        tpv[(size_t)tp_of[c0] * D.Kp + e] = Th[(size_t)t * K + (direct ? q : anti(q))];
+                    }
+                }
+                std::vector<int32_t> ranti(roff.size());
+                for (size_t e = 0; e < roff.size(); ++e) {
+                    if (roff[e] == zero_row) {
+                        ranti[e] = ntp * 512;
+                        continue;
+                    }
+                    const int c = type_code[roff[e] / (64 * (int32_t)sizeof(float2))];
+                    const int c0 = std::min(c, 342 - c);
+                    ranti[e] = tp_of[c0] * 512 | (c != c0 ? 504 : 0);
+                }
+                if ((r = upload(o, &D.Tp, tpv.data(), (int64_t)tpv.size()))) return r;
+                if ((r = upload(o, &D.aperm, ap.data(), D.Kp))) return r;
+                if ((r = upload(o, &D.rec_off_anti, ranti.data(), (int64_t)ranti.size()))) return r;
             }
             {
                 std::vector<int32_t> bs(H.nbox);
@@ -1362,7 +1435,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-        if (variant < 0 || variant > 6) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant < 0 || variant > 7) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         o->lev[level].m2l_variant = variant;
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)

@@ -98,6 +98,15 @@ int cu_count();
 // 3 the same with a 32-sample slice and half-waves on record pairs (one RHS;
 // several RHS take 2);
 // max_wg caps the resident workgroups (0: the CU count)
+// One RHS, antipodal slices (operators of one offset of each +-pair,
+// mirrored lanes for the other): Tp [ntp][Kp] operators in slice-lane
+// order, aperm [Kp] slice lane -> sample (-1 past the end), record slots
+// pair * 512 | (negated ? 504 : 0); max_wg as for m2l_rec
+hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_start,
+                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
+                    const float2 *Tp, const int32_t *aperm, int64_t Kp, const float2 *S,
+                    float2 *Lout, hipStream_t s, int max_wg = 0);
+
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,

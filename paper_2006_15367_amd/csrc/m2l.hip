@@ -349,7 +349,7 @@ hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start
 // batches past the end of the list are fetched and never used (they read
 // the next list or the appended records).  The spectra are read through a buffer resource based
 // at the source (scalar address arithmetic only).
-template <int NO>
+template <int NO, bool ANTI = false>
 __device__ __forceinline__ void m2l_rec_parent1(const char *Tsb, int lane8, int e0, int e1,
                                                 const int32_t *__restrict__ rec_src,
                                                 const int32_t *__restrict__ rec_off,
@@ -384,7 +384,9 @@ __device__ __forceinline__ void m2l_rec_parent1(const char *Tsb, int lane8, int 
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int i = 0; i < NO; ++i) {
-                const float2 tv = *(const float2 *)(Tsb + (of[u][i] + lane8));
+                // ANTI: the offset carries the mirror mask in its low bits
+                const int a = ANTI ? (of[u][i] ^ lane8) : (of[u][i] + lane8);
+                const float2 tv = *(const float2 *)(Tsb + a);
                 acc[i][0] = cfma(tv, v[u], acc[i][0]);
             }
     };
@@ -705,6 +707,111 @@ k_m2l_rec_half(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict
                 if (i < no) Lout[(int64_t)(o0 + i) * K + k] = acc[i];
         }
     }
+}
+
+// One right-hand side with antipodal slices.  The operator of offset -d is
+// that of d at the opposite direction, T_{-d}(k) = T_d(-k), and the grid
+// holds every direction's opposite (Gauss-Legendre nodes symmetric about
+// the equator, an even number of phi samples).  A slice is 32 directions
+// and their 32 opposites, ordered so that lane l and lane l ^ 63 are
+// opposite (aperm: slice lane -> sample, -1 past the end); LDS then needs
+// the operators of one offset of each +-pair only, (158 + 1) x 64 x 8 B,
+// and two workgroups share a CU.  A record slot holds
+// pair * 512 | (negated ? 504 : 0), so the lane's LDS address is that
+// value XOR (8 lane): the mirrored lane for a negated offset, at the cost
+// of the addition it replaces.  Parents are scheduled as in the balanced
+// schedule of k_m2l_rec.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *__restrict__ child_start,
+           const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
+           const int32_t *__restrict__ rec_off, const float2 *__restrict__ Tp,
+           const int32_t *__restrict__ aperm, int64_t Kp, const float2 *__restrict__ S,
+           int nkc, int nrange, float2 *__restrict__ Lout)
+{
+    extern __shared__ float2 Ts[];  // [ntp + 1][64], row ntp = 0
+    __shared__ int next_parent;
+    const int64_t w = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int kc = (int)(w % nkc);
+    const int64_t k0 = (int64_t)kc * 64;
+    stage_t_slice<64>(Ts, Tp, ntp, Kp, k0);
+    for (int idx = threadIdx.x; idx < 64; idx += blockDim.x)
+        Ts[ntp * 64 + idx] = make_float2(0.f, 0.f);
+    if (threadIdx.x == 0) next_parent = 0;
+    __syncthreads();
+    const char *Tsb = (const char *)Ts;
+    const int lane = threadIdx.x & 63;
+    const int lane8 = lane * 8;
+    const int k = aperm[k0 + lane];
+    const bool valid = k >= 0;
+    // (a multiple of 8 below 2^31, as the mask states: the value's two
+    // 32-bit loads merge into one)
+    const uint32_t voff = ((uint32_t)(valid ? k : 0) * (uint32_t)sizeof(float2)) & 0x7ffffff8u;
+    const uint64_t sstride = (uint64_t)K * sizeof(float2);
+    const char *Sb = (const char *)S;
+    const int64_t total = rec_start[nparent];
+    const int64_t rg = w / nkc;
+    auto lower = [&](int64_t target) -> int64_t {
+        int64_t lo = 0, hi = nparent;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)__builtin_amdgcn_readfirstlane(rec_start[mid]) < target) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int64_t pbeg = rg == 0 ? 0 : lower(total * rg / nrange);
+    const int64_t pend = rg == nrange - 1 ? nparent : lower(total * (rg + 1) / nrange);
+    auto take = [&]() -> int64_t {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&next_parent, 1);
+        return pbeg + __builtin_amdgcn_readfirstlane(t);
+    };
+    for (int64_t P = take(); P < pend; P = take()) {
+        const int o0 = __builtin_amdgcn_readfirstlane(child_start[P]);
+        const int no = __builtin_amdgcn_readfirstlane(child_start[P + 1]) - o0;
+        const int e0 = __builtin_amdgcn_readfirstlane(rec_start[P]);
+        const int e1 = __builtin_amdgcn_readfirstlane(rec_start[P + 1]);
+        float2 acc[8][1];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i][0] = make_float2(0.f, 0.f);
+        switch (no) {
+#define ANTI_CASE(N)                                                                          \
+    case N:                                                                                   \
+        m2l_rec_parent1<N, true>(Tsb, lane8, e0, e1, rec_src, rec_off, Sb, sstride, voff, acc); \
+        break;
+            ANTI_CASE(1) ANTI_CASE(2) ANTI_CASE(3) ANTI_CASE(4)
+            ANTI_CASE(5) ANTI_CASE(6) ANTI_CASE(7) ANTI_CASE(8)
+#undef ANTI_CASE
+        default: break;
+        }
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (i < no) Lout[(int64_t)(o0 + i) * K + k] = acc[i][0];
+        }
+    }
+}
+
+hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_start,
+                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
+                    const float2 *Tp, const int32_t *aperm, int64_t Kp, const float2 *S,
+                    float2 *Lout, hipStream_t s, int max_wg)
+{
+    if (nparent == 0 || K == 0) return hipSuccess;
+    const size_t lds = (size_t)(ntp + 1) * 64 * sizeof(float2);
+    if (lds + 16 > 163840) return hipErrorInvalidValue;  // + the static counter
+    if ((uint64_t)K * sizeof(float2) > 0x7fffffffull || Kp % 64 != 0) return hipErrorInvalidValue;
+    const int NW = 16;
+    const int nkc = (int)(Kp / 64);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, 163840 / (lds + 16)));
+    const int ncu = max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count();
+    const int nrange = (int)std::max<int64_t>(
+        1, std::min<int64_t>(per_cu * ncu / nkc, (nparent + NW - 1) / NW));
+    hipLaunchKernelGGL((k_m2l_anti<16>), dim3((unsigned)(nkc * nrange)), dim3(64 * NW), lds, s,
+                       nparent, K, ntp, child_start, rec_start, rec_src, rec_off, Tp, aperm, Kp,
+                       S, nkc, nrange, Lout);
+    return hipGetLastError();
 }
 
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,

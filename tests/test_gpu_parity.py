@@ -142,7 +142,7 @@ def test_field_vs_dense(c1):
     assert e < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_every_m2l_variant(c1, variant):
     torch = c1["torch"]
     say("c1: M2L variant", variant)
@@ -158,6 +158,11 @@ def test_every_m2l_variant(c1, variant):
         for l in range(3, c1["ot"].n_lev + 1):
             ops.set_variant(l, variant)
         phi = _run(c1, ops.matvec, qd)
+        # the locals of every level (M2L plus what L2L brought down)
+        for l in range(3, c1["ot"].n_lev + 1):
+            Lg = ops.copy_spectra(l, 1).cpu().numpy()
+            torch.cuda.synchronize()
+            assert rel_l2(Lg, c1["inter"]["L"][l]) < 1e-4, (variant, l)
         P = _run(c1, ops.matvec, torch.from_numpy(Q).cuda())
     finally:
         for l in range(3, c1["ot"].n_lev + 1):
