@@ -189,8 +189,8 @@ def cpu_baseline(xyz, q, phi_gpu):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sphere262k")
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--bf16x3", action="store_true")
@@ -247,14 +247,17 @@ def main():
         dominant = max(per_kernel, key=lambda k: per_kernel[k][0])
         launches = per_kernel[dominant][1]
 
-        # timed region: K steps.  Eager mode brackets the dominant kernel's
-        # launches with HIP events inside the timed region; graph mode times
-        # them in an equal number of eager steps right after it.
-        if not args.graph:
-            ops.profile_begin([dominant], launches * args.steps + 16)
+        # timed region: K steps.  Eager mode times the dominant kernel's
+        # launches with HIP events inside the timed region, in its last
+        # quarter of the steps (the events the launches record cost about
+        # 3 us per launch, kept off the other three quarters); graph mode
+        # times them in an equal number of eager steps right after it.
+        n_ev = max(1, args.steps // 4)
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        for _ in range(args.steps):
+        for i in range(args.steps):
+            if not args.graph and i == args.steps - n_ev:
+                ops.profile_begin([dominant], launches * n_ev + 16)
             phi = ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
         te = time.perf_counter()
@@ -304,8 +307,10 @@ def main():
                      "matvec_share": round(g_it * ms_per_step / g_ms, 3)}
 
     work = algorithmic_work(tinfo, levels, R, ops.variants("interp"), ops.variants("anterp"))
-    rl = roofline(dominant, work[dominant], dom[0] / args.steps, launches, args.bf16x3)
+    ev_steps = args.steps if args.graph else n_ev  # steps whose launches the events timed
+    rl = roofline(dominant, work[dominant], dom[0] / ev_steps, launches, args.bf16x3)
     alone = roofline(dominant, work[dominant], dom_alone[0] / args.steps, launches, args.bf16x3)
+    rl["event_steps"] = ev_steps
     rl["alone"] = {k: alone[k] for k in ("achieved", "frac", "avg_launch_us", "ms_per_step")}
     rl["traffic"] = recorded_traffic(dominant, args.workload, R)
     if rl["traffic"] is not None:
@@ -331,6 +336,7 @@ def main():
         "m2l_variant_per_level": ops.variants("m2l"),
         "near_field_fork": {0: "downward pass", 1: "start", 2: "after C2M"}.get(
             ops.variants("p2p")[0], "one stream"),
+        "m2l_cu_share_eighths": ops.variants("p2p")[1],
         "onepass_interp_per_level": ops.variants("interp"),
         "onepass_anterp_per_level": ops.variants("anterp"),
         "roofline": rl,

@@ -341,10 +341,13 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * HBM (ids _S1.._S3), 1 + k one pass with the intermediates in LDS in work
  * split k (children per item, waves per workgroup; 3 splits for the bands
  * 8 -> 13, 2 for 13 -> 20).
- * kernel = MLFMA_K_P2P (one entry, out[0]; the level argument of
- * mlfma_ops_set_variant is ignored): where the concurrent schedule forks the
- * near field, 1 at the start of the matvec, 2 after C2M, 0 at the start of
- * the downward pass, -1 when every kernel runs on the caller's stream.
+ * kernel = MLFMA_K_P2P (the concurrent schedule; two entries): out[0]
+ * where it forks the near field, 1 at the start of the matvec, 2 after C2M,
+ * 0 at the start of the downward pass; out[1] the eighths of the CUs the
+ * M2L workgroups of levels above 3 may hold (4 or 6 from the precompute
+ * timing); both -1 when every kernel runs on the caller's stream.
+ * mlfma_ops_set_variant with this kernel sets the fork point (level != 1,
+ * variant 0..2) or the M2L share (level 1, variant 1..8).
  */
 int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
 /* Diagnostics: force a variant of `kernel` on `level` (3..n_levels; for the

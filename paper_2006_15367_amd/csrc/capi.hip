@@ -92,6 +92,9 @@ struct mlfma_ops_s {
     // concurrent: where the near field forks: 0 start of the downward pass,
     // 1 start of the matvec, 2 after C2M
     int near_fork = 0;
+    // concurrent: eighths of the CUs the M2L workgroups of levels > 3 may
+    // hold (timed at precompute with the fork point)
+    int m2l_share8 = 6;
     // GMRES workspace: Krylov basis [(gm_cap + 1) x n], work vector,
     // dot-product partials, coefficient vector (allocated on first solve)
     int gm_cap = 0;
@@ -130,9 +133,9 @@ struct mlfma_ops_s {
 // events when that id is being timed
 #define LAUNCH(id, x)                                           \
     do {                                                        \
-        const bool _p = prof_start(o, (id), s);                 \
+        const int _p = prof_start(o, (id), s);                  \
         hipError_t _e = (x);                                    \
-        if (_p) prof_stop(o, s);                                \
+        if (_p) prof_stop(o, s, _p);                            \
         if (_e != hipSuccess) return check_hip(_e, #x);         \
     } while (0)
 
@@ -144,16 +147,32 @@ struct Planner {
     void add(int64_t b) { bytes += (b + 255) / 256 * 256; }
 };
 
-bool prof_start(mlfma_ops_s *o, int id, hipStream_t s)
+// Timing of one launcher call: 0 not timed; 1 event markers recorded on
+// the stream before and after the call; 2 (M2L) events handed to the
+// launch itself (dev::launch_timing), which records the kernel's own start
+// and end and adds nothing to the stream between kernels.
+int prof_start(mlfma_ops_s *o, int id, hipStream_t s)
 {
-    if (!(o->prof_mask & (1u << id)) || o->prof_used >= o->prof_cap) return false;
-    if (hipEventRecord(o->prof_ev[2 * o->prof_used], s) != hipSuccess) return false;
+    if (!(o->prof_mask & (1u << id)) || o->prof_used >= o->prof_cap) return 0;
     o->prof_id[o->prof_used] = id;
-    return true;
+    if (id == MLFMA_K_M2L) {
+        dev::launch_timing.start = o->prof_ev[2 * o->prof_used];
+        dev::launch_timing.stop = o->prof_ev[2 * o->prof_used + 1];
+        dev::launch_timing.used = false;
+        return 2;
+    }
+    if (hipEventRecord(o->prof_ev[2 * o->prof_used], s) != hipSuccess) return 0;
+    return 1;
 }
 
-void prof_stop(mlfma_ops_s *o, hipStream_t s)
+void prof_stop(mlfma_ops_s *o, hipStream_t s, int mode)
 {
+    if (mode == 2) {
+        const bool used = dev::launch_timing.used;  // false: nothing was launched
+        dev::launch_timing = dev::LaunchTiming();
+        if (used) ++o->prof_used;
+        return;
+    }
     (void)hipEventRecord(o->prof_ev[2 * o->prof_used + 1], s);
     ++o->prof_used;
 }
@@ -448,10 +467,11 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
         hipStream_t s0 = s;
         hipStream_t s = side ? sm : s0;
         DevLevel &D = o->lev[l];
-        // concurrent: the record variants leave a quarter of the CUs (their
-        // workgroups hold a CU's whole LDS) to the upward chain, the
-        // critical path, which otherwise waits for M2L workgroups to retire
-        const int cap = side ? dev::cu_count() - dev::cu_count() / 4 : 0;
+        // concurrent: the record variants take m2l_share8 / 8 of the CUs
+        // (their workgroups hold much or all of a CU's LDS) and leave the
+        // rest to the upward chain, the critical path, which otherwise
+        // waits for M2L workgroups to retire
+        const int cap = side ? dev::cu_count() * o->m2l_share8 / 8 : 0;
         LAUNCH(MLFMA_K_M2L, launch_m2l(o, l, D.m2l_variant, R, s, cap));
         return MLFMA_OK;
     };
@@ -550,24 +570,42 @@ int tune_schedule(mlfma_ops_s *o)
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     float best = 1e30f;
-    int best_fork = 0;
+    int best_fork = 0, best_share = 6;
     int rc = MLFMA_OK;
-    for (int mode = 0; mode < 3 && rc == MLFMA_OK; ++mode) {
+    // repetitions per configuration: about 10 ms of matvecs (3 to 20), so
+    // that short matvecs are timed above the run-to-run noise
+    int reps = 3;
+    {
+        float t1 = 0.f;
+        rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
+        if (rc == MLFMA_OK && hipEventRecord(e0, s) == hipSuccess) {
+            rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
+            if (rc == MLFMA_OK && hipEventRecord(e1, s) == hipSuccess &&
+                hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&t1, e0, e1) == hipSuccess && t1 > 0.f)
+                reps = std::max(3, std::min(20, (int)(10.f / t1)));
+        }
+    }
+    for (int cfg = 0; cfg < 6 && rc == MLFMA_OK; ++cfg) {
+        const int mode = cfg % 3, share = cfg < 3 ? 6 : 4;
         o->near_fork = mode;
+        o->m2l_share8 = share;
         rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
         float t = 0.f;
         if (rc == MLFMA_OK && hipEventRecord(e0, s) == hipSuccess) {
-            for (int rep = 0; rep < 3 && rc == MLFMA_OK; ++rep)
+            for (int rep = 0; rep < reps && rc == MLFMA_OK; ++rep)
                 rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
             if (rc == MLFMA_OK && hipEventRecord(e1, s) == hipSuccess &&
                 hipEventSynchronize(e1) == hipSuccess &&
                 hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best) {
                 best = t;
                 best_fork = mode;
+                best_share = share;
             }
         }
     }
     o->near_fork = best_fork;
+    o->m2l_share8 = best_share;
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1425,6 +1463,7 @@ int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
     }
     if (kernel == MLFMA_K_P2P) {
         if (max_entries >= 1) out[0] = o->side[0] ? o->near_fork : -1;
+        if (max_entries >= 2) out[1] = o->side[0] ? o->m2l_share8 : -1;
         return MLFMA_OK;
     }
     return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
@@ -1449,9 +1488,14 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
         (kernel == MLFMA_K_INTERP ? o->lev[level].interp_variant : o->lev[level].anterp_variant) =
             variant;
     } else if (kernel == MLFMA_K_P2P) {
-        if (variant < 0 || variant > 2) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         if (!o->side[0]) return fail(MLFMA_EINVAL, "ops_set_variant: one-stream handle has no schedule");
-        o->near_fork = variant;
+        if (level == 1) {
+            if (variant < 1 || variant > 8) return fail(MLFMA_EINVAL, "ops_set_variant: bad M2L share %d", variant);
+            o->m2l_share8 = variant;
+        } else {
+            if (variant < 0 || variant > 2) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+            o->near_fork = variant;
+        }
     } else {
         return fail(MLFMA_EINVAL, "ops_set_variant: kernel %d has no variants", kernel);
     }

@@ -91,6 +91,16 @@ hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start,
 // source) in the LDS slice of 64 samples (row ntypes = zeros: no interaction);
 // each parent's records are padded to a multiple of 4 with zero records
 // compute units of the current device
+// Timing of the next M2L launch: when start is set, the M2L launchers
+// launch with hipExtLaunchKernelGGL and these events, which the dispatch
+// itself records at its start and end (no marker packets in the stream
+// between kernels), and set used.  The caller arms and disarms it.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+extern thread_local LaunchTiming launch_timing;
+
 int cu_count();
 
 // schedule: 0 contiguous parent ranges, 1 the slice-major sweep for many

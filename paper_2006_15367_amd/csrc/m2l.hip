@@ -4,6 +4,7 @@
 // observer from L2, operator slice in LDS, sibling groups, sibling groups
 // with per-source records); the autotuner picks one per level.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
@@ -12,6 +13,21 @@
 
 namespace mlfma {
 namespace dev {
+
+thread_local LaunchTiming launch_timing;
+
+// hipLaunchKernelGGL, or hipExtLaunchKernelGGL with the armed timing events
+#define M2L_LAUNCH(kernel, grid, block, shm, stream, ...)                                   \
+    do {                                                                                     \
+        if (launch_timing.start) {                                                           \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, launch_timing.start,     \
+                                  launch_timing.stop, 0, __VA_ARGS__);                       \
+            launch_timing.used = true;                                                       \
+        } else {                                                                             \
+            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);               \
+        }                                                                                    \
+    } while (0)
+
 
 // Compute units of the current device (cached per device).
 int cu_count()
@@ -222,7 +238,7 @@ hipError_t m2l_sg(int64_t nparent, int64_t K, int ntypes, const int32_t *child_s
               (unsigned)((R + RC - 1) / RC));
     dim3 block(1024);
 #define M2L_SG(RCV, KCV)                                                                 \
-    hipLaunchKernelGGL((k_m2l_sg<RCV, KCV>), grid, block, lds, s, nparent, K, ntypes,    \
+    M2L_LAUNCH((k_m2l_sg<RCV, KCV>), grid, block, lds, s, nparent, K, ntypes,    \
                        child_start, nbr_start, nbr_idx, base, typemap, T, S, R, ppb, Lout)
     if (RC == 1) {
         if (KC == 32) M2L_SG(1, 32); else M2L_SG(1, 16);
@@ -318,7 +334,7 @@ hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start
               (unsigned)((R + RC - 1) / RC));
     dim3 block(1024);
 #define M2L_LDS(RCV, KCV)                                                                \
-    hipLaunchKernelGGL((k_m2l_lds<RCV, KCV>), grid, block, lds, s, nbox, K, ntypes,      \
+    M2L_LAUNCH((k_m2l_lds<RCV, KCV>), grid, block, lds, s, nbox, K, ntypes,      \
                        far_start, far_src, far_type, T, S, R, opb, Lout)
     if (RC == 1) {
         if (KC == 32) M2L_LDS(1, 32); else M2L_LDS(1, 16);
@@ -808,7 +824,7 @@ hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_st
     const int ncu = max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count();
     const int nrange = (int)std::max<int64_t>(
         1, std::min<int64_t>(per_cu * ncu / nkc, (nparent + NW - 1) / NW));
-    hipLaunchKernelGGL((k_m2l_anti<16>), dim3((unsigned)(nkc * nrange)), dim3(64 * NW), lds, s,
+    M2L_LAUNCH((k_m2l_anti<16>), dim3((unsigned)(nkc * nrange)), dim3(64 * NW), lds, s,
                        nparent, K, ntp, child_start, rec_start, rec_src, rec_off, Tp, aperm, Kp,
                        S, nkc, nrange, Lout);
     return hipGetLastError();
@@ -829,7 +845,7 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
         const int nkc2 = (int)((K + 31) / 32);
         const int slots = 2 * (max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count());
         const int nr = (int)std::max<int64_t>(1, std::min<int64_t>(slots / nkc2, (nparent + NW - 1) / NW));
-        hipLaunchKernelGGL((k_m2l_rec_half<16>), dim3((unsigned)(nkc2 * nr)), dim3(64 * NW), lds2, s,
+        M2L_LAUNCH((k_m2l_rec_half<16>), dim3((unsigned)(nkc2 * nr)), dim3(64 * NW), lds2, s,
                            nparent, K, ntypes, child_start, rec_start, rec_src, rec_off, T, S,
                            nkc2, nr, Lout);
         return hipGetLastError();
@@ -865,7 +881,7 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
         grid = dim3((unsigned)(nkc * nrange), 1, (unsigned)nz);
     }
 #define M2L_REC(RCV, NWV)                                                                      \
-    hipLaunchKernelGGL((k_m2l_rec<RCV, NWV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
+    M2L_LAUNCH((k_m2l_rec<RCV, NWV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
                        child_start, rec_start, rec_src, rec_off, T, S, R, nkc, nrange, nwg,   \
                        schedule == 2 ? 1 : 0, Lout)
     if (RC == 1) M2L_REC(1, 16);
@@ -882,13 +898,13 @@ hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start, const int32_t 
     const int64_t waves = nbox * ((K + 63) / 64);
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (R == 1)
-        hipLaunchKernelGGL(k_m2l<1>, dim3(blocks, 1), dim3(256), 0, s, nbox, K, far_start,
+        M2L_LAUNCH(k_m2l<1>, dim3(blocks, 1), dim3(256), 0, s, nbox, K, far_start,
                            far_src, far_type, T, S, R, Lout);
     else if (R <= 4)
-        hipLaunchKernelGGL(k_m2l<4>, dim3(blocks, 1), dim3(256), 0, s, nbox, K, far_start,
+        M2L_LAUNCH(k_m2l<4>, dim3(blocks, 1), dim3(256), 0, s, nbox, K, far_start,
                            far_src, far_type, T, S, R, Lout);
     else
-        hipLaunchKernelGGL(k_m2l<8>, dim3(blocks, (R + 7) / 8), dim3(256), 0, s, nbox, K,
+        M2L_LAUNCH(k_m2l<8>, dim3(blocks, (R + 7) / 8), dim3(256), 0, s, nbox, K,
                            far_start, far_src, far_type, T, S, R, Lout);
     return hipGetLastError();
 }

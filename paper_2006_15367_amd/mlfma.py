@@ -339,14 +339,15 @@ class Operators:
 
     def variants(self, kernel="m2l"):
         """Per-level kernel variant chosen by the autotuner (-1: no kernel).
-        kernel="p2p": one entry, where the concurrent schedule forks the near
-        field (1 at the start, 2 after C2M, 0 at the downward pass, -1 one
-        stream)."""
+        kernel="p2p": the concurrent schedule, [where it forks the near field
+        (1 at the start, 2 after C2M, 0 at the downward pass), eighths of the
+        CUs the M2L workgroups of levels > 3 may hold]; [-1, -1] on one
+        stream."""
         nl = self.tree.info()["n_levels"]
-        out = np.full(max(nl, 1), -1, np.int32)
+        out = np.full(2 if kernel == "p2p" else max(nl, 1), -1, np.int32)
         _check(_load().mlfma_ops_variants(self._h, KERNELS.index(kernel), out.ctypes.data,
                                           out.size), "mlfma_ops_variants")
-        return out[:1].tolist() if kernel == "p2p" else out[:nl].tolist()
+        return out.tolist() if kernel == "p2p" else out[:nl].tolist()
 
     def set_variant(self, level, variant, kernel="m2l"):
         _check(_load().mlfma_ops_set_variant(self._h, KERNELS.index(kernel), int(level),

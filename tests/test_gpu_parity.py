@@ -281,20 +281,24 @@ def test_concurrent_schedule_equals_one_stream(c1):
     n = c1["xyz"].shape[0]
     Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
     Qd = torch.from_numpy(Q).cuda()
-    tuned = ops.variants("p2p")[0]
-    assert tuned in (0, 1, 2) and ops1.variants("p2p") == [-1]
+    tuned, share = ops.variants("p2p")
+    assert tuned in (0, 1, 2) and share in (4, 6) and ops1.variants("p2p") == [-1, -1]
     try:
-        for fork in (0, 1, 2):  # near field forked at the downward pass / start / after C2M
+        # near field forked at the downward pass / start / after C2M; M2L
+        # of levels > 3 on half, three quarters or all of the CUs
+        for fork, sh in ((0, 6), (1, 6), (2, 6), (1, 4), (2, 8)):
             ops.set_variant(0, fork, kernel="p2p")
+            ops.set_variant(1, sh, kernel="p2p")
             for rep in range(3):
                 a = _run(c1, ops.matvec, Qd)
                 b = _run(c1, ops1.matvec, Qd)
-                assert np.array_equal(a, b), (fork, rep)
+                assert np.array_equal(a, b), (fork, sh, rep)
             fa = _run(c1, ops.field, Qd[:, 0].contiguous())
             fb = _run(c1, ops1.field, Qd[:, 0].contiguous())
-            assert np.array_equal(fa, fb), fork
+            assert np.array_equal(fa, fb), (fork, sh)
     finally:
         ops.set_variant(0, tuned, kernel="p2p")
+        ops.set_variant(1, share, kernel="p2p")
 
 
 def test_graph_replays_match_eager(c1):
