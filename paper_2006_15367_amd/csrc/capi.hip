@@ -42,7 +42,8 @@ struct DevLevel {
     int16_t *typemap = nullptr;      // [343] offset code -> operator or -1
     int m2l_variant = 0;             // 0 per-observer (L2), 1 operators in LDS, 2 sibling groups,
                                      // 3 sibling groups with per-source records, 4 = 3 with
-                                     // the slice-major sweep
+                                     // the slice-major sweep, 5 = 3 record-balanced, 6 = 5 on
+                                     // 32-sample slices, 7 = 5 on antipodal slices
     int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     // antipodal slices (one-RHS variant 7): operators of one offset of each
