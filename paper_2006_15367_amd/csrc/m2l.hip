@@ -1,8 +1,9 @@
 // M2L (Sec. 3.2.3): the diagonal translation L_b += sum_{b' in IL(b)}
 // T_{l,t(b,b')} (.) S_b' over the interaction lists, elementwise over the
-// K_l samples and every right-hand side.  Four kernel variants (per
-// observer from L2, operator slice in LDS, sibling groups, sibling groups
-// with per-source records); the autotuner picks one per level.
+// K_l samples and every right-hand side.  Kernel forms: per observer from
+// L2, operator slice in LDS, sibling groups, and sibling groups with
+// per-source records (three parent schedules, a 32-sample slice and
+// antipodal slices for one RHS); the autotuner picks one per level.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -27,7 +28,6 @@ thread_local LaunchTiming launch_timing;
             hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);               \
         }                                                                                    \
     } while (0)
-
 
 // Compute units of the current device (cached per device).
 int cu_count()
