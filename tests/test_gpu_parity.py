@@ -329,3 +329,26 @@ def test_graph_replays_match_eager(c1):
         psi = ops_g.adjoint(qd, stream=st)
     st.synchronize()
     assert rel_l2(psi.cpu().numpy(), _run(c1, c1["gops"].adjoint, qd)) < 1e-6
+
+
+def test_variant_and_schedule_limits(c1):
+    """mlfma_ops_set_variant rejects unknown kernel forms and schedule
+    settings with MLFMA_EINVAL and leaves the handle as it was."""
+    G = c1["G"]
+    ops = c1["gops"]
+    say("c1: variant and schedule limits")
+    nl = c1["ot"].n_lev
+    before = (ops.variants("m2l"), ops.variants("p2p"))
+    bad = [
+        (3, 8, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
+        (0, 3, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
+        (nl, 0, "interp"),
+    ]
+    for level, variant, kernel in bad:
+        with pytest.raises(G.MlfmaError) as e:
+            ops.set_variant(level, variant, kernel=kernel)
+        assert e.value.status == G.EINVAL, (level, variant, kernel)
+    assert (ops.variants("m2l"), ops.variants("p2p")) == before
+    ops1 = G.Operators(c1["gt"], K, W.DIGITS, max_rhs=1, one_stream=True, autotune=False)
+    with pytest.raises(G.MlfmaError):
+        ops1.set_variant(0, 1, kernel="p2p")  # one stream: no schedule to set
