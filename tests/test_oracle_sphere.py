@@ -196,3 +196,25 @@ def test_truncation_orders_per_level():
     # 3 digits: 0.25 -> 8, 0.5 -> 13, 1 -> 20, 2 -> 33, 4 -> 57, 8 -> 104, 16 -> 196
     got = [M.truncation_order(K, a, 3) for a in (0.25, 0.5, 1, 2, 4, 8, 16)]
     assert got == [8, 13, 20, 33, 57, 104, 196]
+
+
+@pytest.mark.parametrize("L", [8, 13, 20])
+def test_translation_operator_antipodal_symmetry(L):
+    """T_{-X}(k) = T_X(-k): P_l(-u) = (-1)^l P_l(u) is the same sign flip
+    whether the offset or the direction is negated.  On the grid, -k of
+    sample (i, j) is sample (L - i, j + L + 1) (Gauss-Legendre nodes
+    symmetric about the equator, 2L + 2 phi samples): the one-RHS M2L form
+    that keeps one offset of each +-pair in LDS reads the other through
+    that mirror."""
+    g = sphere.SphereGrid(L)
+    nth, nph = g.ntheta, g.nphi
+    q = np.arange(g.K)
+    anti = (nth - 1 - q // nph) * nph + (q % nph + nph // 2) % nph
+    assert np.array_equal(anti[anti], q) and np.all(anti != q)
+    assert np.allclose(g.khat[anti], -g.khat, atol=1e-15)
+    a = 0.25
+    for d in [(2, 0, 0), (3, -1, 2), (-2, 3, 3), (0, -2, 1)]:
+        X = np.array(d, dtype=float) * a
+        tp = M.translation_operator(K, L, X, g)
+        tm = M.translation_operator(K, L, -X, g)
+        assert np.max(np.abs(tm - tp[anti])) <= 1e-12 * np.max(np.abs(tp))
