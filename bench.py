@@ -84,8 +84,8 @@ def algorithmic_work(tinfo, levels, R, onepass_up=None, onepass_down=None):
             g1 = 4.0 * Bc * p["ntheta"] * p["nphi"] * M + 8.0 * Bc * p["K"]
             g2 = 4.0 * Bc * M * c["ntheta"] * p["ntheta"]
             g3 = 4.0 * Bc * c["ntheta"] * M * c["nphi"]
-            up = bool(onepass_up and onepass_up[l - 1] == 1)
-            dn = bool(onepass_down and onepass_down[l - 1] == 1)
+            up = bool(onepass_up and onepass_up[l - 1] >= 1)
+            dn = bool(onepass_down and onepass_down[l - 1] >= 1)
             if up:
                 w["interp"]["flops"] += f1 + f2 + f3
                 w["interp"]["bytes"] += 8.0 * (Bc * c["K"] + Bp * p["K"])

@@ -133,8 +133,10 @@ int mlfma_build_tree(const double *xyz, int64_t n, double leaf_size,
 
 /*
  * Replace the point coordinates while keeping the tree's topology (used for
- * finite-difference checks of position gradients).  Every point must stay in
- * its leaf box (same floor index); otherwise ERANGE and nothing changes.
+ * finite-difference checks of position gradients).  Every point must stay
+ * inside the root cube and in its leaf box (same floor index); otherwise
+ * ERANGE and nothing changes.  Existing handles wait for the device to be
+ * idle before their next call uploads the new positions.
  * Takes effect for operator handles created afterwards and, for existing
  * handles, at their next call (the device copy is refreshed lazily).
  */
@@ -160,7 +162,10 @@ int mlfma_update_positions(mlfma_tree_t t, const double *xyz);
  *   flags   MLFMA_FP32 or MLFMA_BF16X3_INTERP
  * Errors: EINVAL (k <= 0 or non-finite, digits, max_rhs, flags, a leaf box
  *         with k sqrt(3) leaf_size < 1 while the tree has far-field levels --
- *         the diagonal form is not accurate there), ENOMEM (device memory or
+ *         the diagonal form is not accurate there -- or a leaf box larger
+ *         than about 72 wavelengths, k 2 sqrt(3) leaf_size / (2 pi) > 250,
+ *         beyond the range of the near field's FP32 phase evaluation),
+ *         ENOMEM (device memory or
  *         the limit of mlfma_set_device_memory_limit), EDEVICE.
  * The ops handle keeps a reference to the tree (destroying the tree first is
  * allowed).

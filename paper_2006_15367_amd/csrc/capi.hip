@@ -280,7 +280,11 @@ int refresh_positions(mlfma_ops_s *o)
 {
     if (o->pos_version == o->tree->pos_version) return MLFMA_OK;
     std::vector<float4> p = point_offsets(*o->tree);
-    hipError_t e = hipMemcpy(o->pts, p.data(), p.size() * sizeof(float4), hipMemcpyHostToDevice);
+    // calls still running on other streams (the caller's, the library's
+    // side streams) read the positions: let them finish before the upload
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return check_hip(e, "position upload: device synchronize");
+    e = hipMemcpy(o->pts, p.data(), p.size() * sizeof(float4), hipMemcpyHostToDevice);
     if (e != hipSuccess) return check_hip(e, "position upload");
     o->pos_version = o->tree->pos_version;
     return MLFMA_OK;
@@ -747,6 +751,14 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE | MLFMA_USE_GRAPH |
                             MLFMA_ONE_STREAM))
         return fail(MLFMA_EINVAL, "precompute: unknown flags");
+    // the near-field kernels evaluate exp(ikr) on the hardware sine/cosine,
+    // whose argument (in turns, k r / 2 pi) must stay within +-256; near
+    // pairs are at most 2 sqrt(3) leaf apart
+    if (k * 2.0 * std::sqrt(3.0) * t->leaf / (2.0 * M_PI) > 250.0)
+        return fail(MLFMA_EINVAL,
+                    "precompute: leaf boxes of %g wavelengths exceed the near-field phase range "
+                    "(at most about 72 wavelengths)",
+                    k * t->leaf / (2.0 * M_PI));
     if (t->n_lev >= 3 && k * std::sqrt(3.0) * t->leaf < 1.0)
         return fail(MLFMA_EINVAL,
                     "precompute: leaf boxes too small for the diagonal form (k sqrt(3) a = %g < 1)",

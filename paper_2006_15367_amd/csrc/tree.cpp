@@ -312,7 +312,15 @@ int update_positions(Tree *t, const double *xyz)
             double v = xyz[3 * i + a];
             if (!std::isfinite(v))
                 return fail(MLFMA_EINVAL, "update_positions: non-finite coordinate");
-            int64_t f = (int64_t)std::floor((v - t->origin[a]) / t->leaf);
+            // the point must stay inside the root cube (up to the rounding
+            // of a point on its faces, which build_tree clamps) and in its
+            // leaf box: the leaf expansions and the near/far split assume it
+            const double u = (v - t->origin[a]) / t->leaf;
+            const double tol = 1e-9 * (double)nside;
+            if (!(u >= -tol && u <= (double)nside + tol))
+                return fail(MLFMA_ERANGE, "update_positions: point %lld left the root cube",
+                            (long long)i);
+            int64_t f = (int64_t)std::floor(u);
             f = std::min<int64_t>(std::max<int64_t>(f, 0), nside - 1);
             if (f != c[a])
                 return fail(MLFMA_ERANGE, "update_positions: point %lld left its leaf box",

@@ -38,3 +38,28 @@ def test_recorded_traffic_follows_the_source(tmp_path, monkeypatch):
     assert bench.recorded_traffic("m2l", "spheroid1m", 1) is None  # no profile
     src.write_bytes(b"// kernel source, changed\n")
     assert bench.recorded_traffic("m2l", "sphere262k", 1) is None
+
+
+def _fake_levels():
+    tinfo = {"n_points": 1000, "n_levels": 4, "n_p2p_pairs": 50000}
+    levels = [{"level": 1, "nbox": 1}, {"level": 2, "nbox": 8},
+              {"level": 3, "nbox": 20, "L": 13, "ntheta": 14, "nphi": 28, "K": 392,
+               "n_far": 300, "n_types": 40},
+              {"level": 4, "nbox": 100, "L": 8, "ntheta": 9, "nphi": 18, "K": 162,
+               "n_far": 2000, "n_types": 100}]
+    return tinfo, levels
+
+
+def test_onepass_work_split_books_on_the_onepass_kernel():
+    """A one-pass pair in any work split (variant 1 + k) books all of its
+    work on "interp"/"anterp" and none on the staged kernels."""
+    tinfo, levels = _fake_levels()
+    staged = bench.algorithmic_work(tinfo, levels, 4, [-1, -1, 0, -1], [-1, -1, 0, -1])
+    for v in (1, 2, 3):
+        w = bench.algorithmic_work(tinfo, levels, 4, [-1, -1, v, -1], [-1, -1, v, -1])
+        for k in ("interp_s1", "interp_s2", "interp_s3", "anterp_s1", "anterp_s2", "anterp_s3"):
+            assert w[k]["flops"] == 0 and w[k]["bytes"] == 0, (v, k)
+        up = sum(staged[k]["flops"] for k in ("interp_s1", "interp_s2", "interp_s3"))
+        dn = sum(staged[k]["flops"] for k in ("anterp_s1", "anterp_s2", "anterp_s3"))
+        assert w["interp"]["flops"] == up > 0
+        assert w["anterp"]["flops"] == dn > 0

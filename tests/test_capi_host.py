@@ -98,6 +98,37 @@ def test_update_positions_keeps_boxes():
     assert e.value.status == G.ERANGE
 
 
+def test_update_positions_refuses_leaving_the_root_cube():
+    # a point of a boundary leaf moved outward stays in the clamped leaf
+    # index but leaves the cube and its box: refused, nothing changes
+    xyz, _ = W.make("sphere4k")
+    t = G.Tree(xyz, W.LEAF_SIZE)
+    i = int(np.argmax(xyz[:, 0]))
+    for shift in (5.0, 0.3, 0.26):
+        moved = xyz.copy()
+        moved[i, 0] += shift
+        with pytest.raises(G.MlfmaError) as e:
+            t.update_positions(moved)
+        assert e.value.status == G.ERANGE, shift
+    moved = xyz.copy()
+    moved[i, 0] -= 1e-6          # inward, same box
+    t.update_positions(moved)
+
+
+def test_precompute_refuses_leaves_beyond_the_phase_range():
+    # near pairs up to 2 sqrt(3) leaf apart must stay within 250 turns of
+    # the hardware sine: leaves of 80 wavelengths are refused before the
+    # device is touched, 60 wavelengths pass that check
+    lib = G._load()
+    rng = np.random.default_rng(3)
+    h = ctypes.c_void_p()
+    xyz = rng.uniform(-10, 10, (64, 3))
+    t = G.Tree(xyz, 80.0)
+    assert lib.mlfma_precompute_operators(t.handle, W.K_WAVENUMBER, 3, 1, 0,
+                                          ctypes.byref(h)) == G.EINVAL
+    assert "phase range" in lib.mlfma_last_error().decode()
+
+
 def test_precompute_argument_errors_and_memory_cap():
     lib = G._load()
     xyz, _ = W.make("sphere4k")
