@@ -15,6 +15,20 @@ def pytest_configure(config):
         "markers", "slow: CPU test that takes more than a few seconds")
 
 
+def pytest_addoption(parser):
+    parser.addoption("--runslow", action="store_true", default=False,
+                     help="also run the CPU tests marked slow (minutes each)")
+
+
+def pytest_collection_modifyitems(config, items):
+    if config.getoption("--runslow"):
+        return
+    skip = pytest.mark.skip(reason="slow CPU test: run with --runslow")
+    for item in items:
+        if "slow" in item.keywords:
+            item.add_marker(skip)
+
+
 @pytest.fixture(scope="session")
 def oracle_dense():
     from oracle import dense
