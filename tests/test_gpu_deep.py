@@ -210,3 +210,37 @@ def test_deep_bf16x3_levels(c2):
     e = rel_l2(phi, c2["ophi"])
     say("deep bf16x3: potential vs FP64 MLFMA", e)
     assert e < 1e-3
+
+
+def test_spheroid_every_level_and_far_part():
+    """The elongated cloud at full size (1,048,576 points, 9 levels, orders
+    8 .. 196 on levels 9 .. 3, K up to 77,618 samples, tip leaves of 1,566
+    points): multipoles and locals of every level, the far part and the
+    potential against the FP64 oracle, same bounds as the sphere."""
+    torch = cuda_or_skip()
+    from oracle import mlfma as M
+    from paper_2006_15367_amd import mlfma as G
+    xyz, q = W.make("spheroid1m")
+    q = q.astype(np.complex128)
+    say("spheroid: FP64 oracle MLFMA (keeps every level)")
+    ot = M.Tree(xyz, W.LEAF_SIZE)
+    oops = M.Operators(ot, K, W.DIGITS)
+    ophi, inter = M.matvec(ot, oops, q, keep=True)
+    assert ot.n_lev == 9 and oops.L[3] == 196 and oops.L[4] == 104
+    say("spheroid: GPU tree and operators")
+    gt = G.Tree(xyz, W.LEAF_SIZE)
+    gops = G.Operators(gt, K, W.DIGITS, max_rhs=1)
+    c = dict(torch=torch, ot=ot, inter=inter, gops=gops)
+    phi = _matvec(c, q)
+    _levels_check(c, "spheroid")
+    qd = torch.from_numpy(q.astype(np.complex64)).cuda()
+    far = gops.matvec_ex(qd, parts=G.FAR)
+    torch.cuda.synchronize()
+    far = far.cpu().numpy()
+    ref = np.empty_like(inter["far"][:, 0])
+    ref[ot.perm] = inter["far"][:, 0]
+    ef, mf = rel_l2(far, ref), max_rel(far, ref)
+    e, m = rel_l2(phi, ophi), max_rel(phi, ophi)
+    say("spheroid: far rel %.2e max %.2e; potential rel %.2e max %.2e" % (ef, mf, e, m))
+    assert ef < TOL_L and mf < TOL_L
+    assert e < TOL_L and m < TOL_L
