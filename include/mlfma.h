@@ -262,6 +262,33 @@ int mlfma_solve_gmres(mlfma_ops_t ops, const void *b, void *x, double shift_re,
                       double shift_im, int restart, int max_iters, double tol,
                       int *iters, double *rel_residual, void *stream);
 
+/* Bytes of device scratch behind mlfma_solve_gmres_noalloc, per GPU. */
+#define MLFMA_GMRES_SCRATCH_BYTES (64ll << 20)
+
+/*
+ * mlfma_solve_gmres for callers that cannot allocate device memory (code
+ * under HIP graph capture elsewhere in the process, serving loops or
+ * harnesses that forbid hipMalloc): the same solve, arguments, results and
+ * errors, but the Krylov basis, work vector, partial sums and coefficients
+ * live in a fixed device array of MLFMA_GMRES_SCRATCH_BYTES (64 MiB) that
+ * the library's code object holds on every GPU it runs on until the
+ * process ends.  Nothing is allocated or freed on the device (the handle's
+ * own matvec workspace, allocated by mlfma_precompute_operators, is used
+ * as by every matvec).
+ * Size limit: (restart + 2) n complex64 plus (restart + 1) (nb + 1)
+ * complex FP64, nb = min(512, ceil(n / 2048)), each of the four buffers
+ * rounded up to 256 bytes, must fit in MLFMA_GMRES_SCRATCH_BYTES (for
+ * n = 262,144: restart up to 29); larger requests return MLFMA_ENOMEM
+ * before any work is enqueued.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on the same GPU (other threads, other handles, other streams) race and
+ * must be serialised by the caller.  The array keeps the last call's
+ * contents; the solve initialises everything it reads.
+ */
+int mlfma_solve_gmres_noalloc(mlfma_ops_t ops, const void *b, void *x, double shift_re,
+                              double shift_im, int restart, int max_iters, double tol,
+                              int *iters, double *rel_residual, void *stream);
+
 void mlfma_destroy_ops(mlfma_ops_t ops);
 void mlfma_destroy_tree(mlfma_tree_t t);
 

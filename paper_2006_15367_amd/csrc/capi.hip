@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1113,7 +1114,7 @@ int mlfma_matvec_ex(mlfma_ops_t ops, const void *q, void *phi, int64_t nrhs, int
 // ----------------------------------------------------------- GMRES solve --
 namespace {
 
-void free_alloc(mlfma_ops_s *o, void *p)
+static void free_alloc(mlfma_ops_s *o, void *p)
 {
     if (!p) return;
     auto it = std::find(o->allocs.begin(), o->allocs.end(), p);
@@ -1121,7 +1122,7 @@ void free_alloc(mlfma_ops_s *o, void *p)
     (void)hipFree(p);
 }
 
-int gm_workspace(mlfma_ops_s *o, int m)
+static int gm_workspace(mlfma_ops_s *o, int m)
 {
     if (m <= o->gm_cap) return MLFMA_OK;
     free_alloc(o, o->gm_V);
@@ -1148,11 +1149,71 @@ int gm_workspace(mlfma_ops_s *o, int m)
     return MLFMA_OK;
 }
 
-}  // namespace
+// Device scratch of the allocation-free solve: one array per GPU, placed by
+// the code-object loader (no hipMalloc).  Host code never passes the
+// array's name to a kernel or a copy: it takes the device address that
+// hipGetSymbolAddress returns, once per device, and uses only that.
+static __device__ __align__(256) unsigned char scratch[MLFMA_GMRES_SCRATCH_BYTES];
 
-int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, double shift_im,
-                      int restart, int max_iters, double tol, int *iters, double *rel_residual,
-                      void *stream)
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+static int scratch_address(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(MLFMA_EDEVICE, "solve_gmres_noalloc: device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(MLFMA_EDEVICE, "solve_gmres_noalloc: hipGetSymbolAddress(scratch): %s",
+                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[device]);
+    return MLFMA_OK;
+}
+
+struct GmBuffers {
+    float2 *V = nullptr, *w = nullptr;
+    double2 *part = nullptr, *c = nullptr;
+};
+
+static int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// The GMRES buffers of restart m carved from the device scratch:
+// V [(m + 1) x n], w [n] complex64, block partials [(m + 1) x nb] and
+// coefficients [m + 1] complex FP64, each at a 256-byte boundary.
+static int gm_static(mlfma_ops_s *o, int m, GmBuffers *out)
+{
+    const int64_t n = o->n, nb = dev::gm_dot_blocks(n);
+    const int64_t bV = align256((int64_t)(m + 1) * n * (int64_t)sizeof(float2));
+    const int64_t bw = align256(n * (int64_t)sizeof(float2));
+    const int64_t bp = align256((int64_t)(m + 1) * nb * (int64_t)sizeof(double2));
+    const int64_t bc = align256((int64_t)(m + 1) * (int64_t)sizeof(double2));
+    const int64_t need = bV + bw + bp + bc;
+    if (need > (int64_t)MLFMA_GMRES_SCRATCH_BYTES)
+        return fail(MLFMA_ENOMEM,
+                    "solve_gmres_noalloc: n = %lld with restart %d needs %lld bytes of "
+                    "scratch, more than the fixed %lld",
+                    (long long)n, m, (long long)need, (long long)MLFMA_GMRES_SCRATCH_BYTES);
+    unsigned char *base = nullptr;
+    if (int r = scratch_address(o->device, &base)) return r;
+    out->V = reinterpret_cast<float2 *>(base);
+    out->w = reinterpret_cast<float2 *>(base + bV);
+    out->part = reinterpret_cast<double2 *>(base + bV + bw);
+    out->c = reinterpret_cast<double2 *>(base + bV + bw + bp);
+    return MLFMA_OK;
+}
+
+static int gmres_run(mlfma_ops_t o, const void *b, void *x, double shift_re, double shift_im,
+              int restart, int max_iters, double tol, int *iters, double *rel_residual,
+              void *stream, bool noalloc)
 {
     typedef std::complex<double> cd;
     if (iters) *iters = 0;
@@ -1172,19 +1233,30 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
     if (cur != o->device && hipSetDevice(o->device) != hipSuccess)
         return fail(MLFMA_EDEVICE, "hipSetDevice(%d) failed", o->device);
     const int m = restart;
-    int rc = gm_workspace(o, m);
+    GmBuffers wb;
+    int rc = MLFMA_OK;
+    if (noalloc) {
+        rc = gm_static(o, m, &wb);
+    } else {
+        rc = gm_workspace(o, m);
+        wb.V = o->gm_V;
+        wb.w = o->gm_w;
+        wb.part = o->gm_part;
+        wb.c = o->gm_c;
+    }
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = o->n;
     const int nb = dev::gm_dot_blocks(n);
     const float2 *bv = (const float2 *)b;
-    float2 *xv = (float2 *)x, *V = o->gm_V, *w = o->gm_w;
+    float2 *xv = (float2 *)x, *V = wb.V, *w = wb.w;
+    double2 *gpart = wb.part, *gcoef = wb.c;
     auto row = [&](int i) { return V + (int64_t)i * n; };
     std::vector<double2> part((size_t)(m + 1) * nb), coef(m + 1);
     // out[i] = <V_i, u> for i < cnt (FP64 sums of the block partials)
     auto dots = [&](const float2 *Vb, int cnt, const float2 *u, cd *out) -> int {
-        CK(dev::gm_dots(Vb, n, cnt, u, n, nb, o->gm_part, s));
-        CK(hipMemcpyAsync(part.data(), o->gm_part, (size_t)cnt * nb * sizeof(double2),
+        CK(dev::gm_dots(Vb, n, cnt, u, n, nb, gpart, s));
+        CK(hipMemcpyAsync(part.data(), gpart, (size_t)cnt * nb * sizeof(double2),
                           hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         for (int i = 0; i < cnt; ++i) {
@@ -1199,9 +1271,9 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
     };
     // out[i] = <V_i, u> for i < cnt and *uu = <u, u>, one host round trip
     auto dots_norm = [&](int cnt, const float2 *u, cd *out, double *uu) -> int {
-        CK(dev::gm_dots(V, n, cnt, u, n, nb, o->gm_part, s));
-        CK(dev::gm_dots(u, n, 1, u, n, nb, o->gm_part + (size_t)cnt * nb, s));
-        CK(hipMemcpyAsync(part.data(), o->gm_part, (size_t)(cnt + 1) * nb * sizeof(double2),
+        CK(dev::gm_dots(V, n, cnt, u, n, nb, gpart, s));
+        CK(dev::gm_dots(u, n, 1, u, n, nb, gpart + (size_t)cnt * nb, s));
+        CK(hipMemcpyAsync(part.data(), gpart, (size_t)(cnt + 1) * nb * sizeof(double2),
                           hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         for (int i = 0; i <= cnt; ++i) {
@@ -1224,9 +1296,9 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
     // u <- u + sign * sum_{i < cnt} V_i c_i
     auto combine = [&](float2 *u, int cnt, const cd *c, double sign) -> int {
         for (int i = 0; i < cnt; ++i) coef[i] = make_double2(c[i].real(), c[i].imag());
-        CK(hipMemcpyAsync(o->gm_c, coef.data(), (size_t)cnt * sizeof(double2),
+        CK(hipMemcpyAsync(gcoef, coef.data(), (size_t)cnt * sizeof(double2),
                           hipMemcpyHostToDevice, s));
-        CK(dev::gm_combine(u, V, n, cnt, o->gm_c, sign, n, s));
+        CK(dev::gm_combine(u, V, n, cnt, gcoef, sign, n, s));
         return MLFMA_OK;
     };
     // y <- (shift I + A) v
@@ -1327,6 +1399,24 @@ int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, do
     if (iters) *iters = total;
     if (rel_residual) *rel_residual = relres;
     return MLFMA_OK;
+}
+
+}  // namespace
+
+int mlfma_solve_gmres(mlfma_ops_t o, const void *b, void *x, double shift_re, double shift_im,
+                      int restart, int max_iters, double tol, int *iters, double *rel_residual,
+                      void *stream)
+{
+    return gmres_run(o, b, x, shift_re, shift_im, restart, max_iters, tol, iters, rel_residual,
+                     stream, false);
+}
+
+int mlfma_solve_gmres_noalloc(mlfma_ops_t o, const void *b, void *x, double shift_re,
+                              double shift_im, int restart, int max_iters, double tol,
+                              int *iters, double *rel_residual, void *stream)
+{
+    return gmres_run(o, b, x, shift_re, shift_im, restart, max_iters, tol, iters, rel_residual,
+                     stream, true);
 }
 
 int mlfma_field(mlfma_ops_t ops, const void *q, void *grad, int64_t nrhs, int dtype,

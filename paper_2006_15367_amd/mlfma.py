@@ -70,6 +70,10 @@ EXPORTS = {
     "mlfma_solve_gmres": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "mlfma_solve_gmres_noalloc": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p], ctypes.c_int),
     "mlfma_destroy_ops": ([ctypes.c_void_p], None),
     "mlfma_destroy_tree": ([ctypes.c_void_p], None),
     "mlfma_tree_info_get": ([ctypes.c_void_p, ctypes.POINTER(TreeInfo)], ctypes.c_int),
@@ -287,10 +291,13 @@ class Operators:
                "mlfma_matvec_adjoint")
         return out
 
-    def solve(self, b, shift, restart=30, max_iters=300, tol=1e-5, x0=None, stream=None):
+    def solve(self, b, shift, restart=30, max_iters=300, tol=1e-5, x0=None, stream=None,
+              noalloc=False):
         """Solve (shift I + A) x = b by restarted GMRES on the device
-        (mlfma_solve_gmres); b is a complex64 CUDA tensor [n] in caller
-        order.  Returns (x, operator applications, relative residual)."""
+        (mlfma_solve_gmres; with noalloc=True mlfma_solve_gmres_noalloc,
+        whose Krylov basis sits in the library's fixed device scratch); b is
+        a complex64 CUDA tensor [n] in caller order.  Returns (x, operator
+        applications, relative residual)."""
         import torch
         if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.complex64):
             raise TypeError("expected a complex64 CUDA (HIP) tensor")
@@ -301,10 +308,11 @@ class Operators:
         it = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
         sh = complex(shift)
-        _check(_load().mlfma_solve_gmres(self._h, b.data_ptr(), x.data_ptr(), sh.real, sh.imag,
-                                         int(restart), int(max_iters), float(tol),
-                                         ctypes.byref(it), ctypes.byref(rr),
-                                         _stream_ptr(stream)), "mlfma_solve_gmres")
+        name = "mlfma_solve_gmres_noalloc" if noalloc else "mlfma_solve_gmres"
+        _check(getattr(_load(), name)(self._h, b.data_ptr(), x.data_ptr(), sh.real, sh.imag,
+                                      int(restart), int(max_iters), float(tol),
+                                      ctypes.byref(it), ctypes.byref(rr), _stream_ptr(stream)),
+               name)
         return x, it.value, rr.value
 
     def field(self, q, parts=0, stream=None):

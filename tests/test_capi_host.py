@@ -184,8 +184,10 @@ def test_solve_gmres_argument_errors():
         (complex(float("inf"), 0), 30, 10, 1e-5),  # shift not finite
         (1j, 30, 10, 1e-5),          # null handle
     ]
-    for sh, restart, maxit, tol in bad:
-        st = lib.mlfma_solve_gmres(None, None, None, sh.real, sh.imag, restart, maxit, tol,
-                                   ctypes.byref(it), ctypes.byref(rr), None)
-        assert st == G.EINVAL, (sh, restart, maxit, tol)
-        assert it.value == 0 and rr.value == 0.0
+    for fn in (lib.mlfma_solve_gmres, lib.mlfma_solve_gmres_noalloc):
+        for sh, restart, maxit, tol in bad:
+            it.value, rr.value = 7, 3.0
+            st = fn(None, None, None, sh.real, sh.imag, restart, maxit, tol,
+                    ctypes.byref(it), ctypes.byref(rr), None)
+            assert st == G.EINVAL, (fn, sh, restart, maxit, tol)
+            assert it.value == 0 and rr.value == 0.0
