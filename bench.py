@@ -8,7 +8,7 @@ the timed region; setup (tree, FP64 operator precompute, uploads) is timed
 separately.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                  [--nrhs R] [--bf16x3] [--no-cpu-baseline]
+                  [--nrhs R] [--bf16x3] [--no-cpu-baseline] [--no-extras]
 
 The default workload is the 262,144-point sphere of diameter 16 wavelengths,
 leaf 0.25 wavelength, 3 digits, one right-hand side.
@@ -158,17 +158,78 @@ def roofline(kernel, work, ms_per_step, launches_per_step, bf16x3):
             "ms_per_step": round(ms_per_step, 4)}
 
 
-def cpu_baseline(xyz, q, phi_gpu):
-    """The FP64 oracle MLFMA, untuned, timed on the host cores: one full
-    matvec of the same workload (setup excluded)."""
+# the method's phases (Sec. 2 five-stage list plus the near field) and the
+# kernels that run them; a phase's bound is that of its kernels
+PHASES = {"gather": ["gather"], "p2p": ["p2p"], "c2m": ["c2m"],
+          "m2m": ["interp_s1", "interp_s2", "interp_s3", "interp"],
+          "m2l": ["m2l"],
+          "l2l": ["anterp_s1", "anterp_s2", "anterp_s3", "anterp"],
+          "l2o": ["l2o"]}
+PHASE_BOUND = {"gather": "hbm", "p2p": "alu", "c2m": "alu", "m2m": "mfma", "m2l": "alu",
+               "l2l": "mfma", "l2o": "alu"}
+
+
+def phase_rooflines(work, per_kernel_ms, bf16x3):
+    """Per phase: algorithmic work, time alone (ms per step, kernels on one
+    stream), achieved rate against the peak of its bound, and the floor
+    time max(bytes / HBM peak, flops / compute peak).  Also the sum of the
+    floors (the whole matvec's roofline time)."""
+    out = {}
+    floor_total = 0.0
+    for ph, ks in PHASES.items():
+        fl = sum(work[k]["flops"] for k in ks)
+        by = sum(work[k]["bytes"] for k in ks)
+        ms = sum(per_kernel_ms.get(k, 0.0) for k in ks)
+        bound = PHASE_BOUND[ph]
+        cpeak = PEAK_BF16_TFLOPS if (bound == "mfma" and bf16x3) else PEAK_FP32_TFLOPS
+        floor_ms = max(by / (PEAK_HBM_GBS * 1e9), fl / (cpeak * 1e12)) * 1e3
+        floor_total += floor_ms
+        if ms <= 0.0:
+            continue
+        if bound == "hbm":
+            ach, peak, unit = by / (ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
+        else:
+            ach, peak, unit = fl / (ms * 1e-3) / 1e12, cpeak, "TFLOP/s"
+        out[ph] = {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                   "frac": round(ach / peak, 4), "ms_alone": round(ms, 4),
+                   "floor_ms": round(floor_ms, 5),
+                   "hbm_GBs": round(by / (ms * 1e-3) / 1e9, 1)}
+    return out, floor_total
+
+
+def dense_baseline(xyz, q, ntgt=2048, seed=11):
+    """The plain O(N^2) FP64 sum (C, OpenMP on the host cores) on a bounded
+    sample of targets: pairs per second and the extrapolated full time."""
+    from oracle import dense
+    from paper_2006_15367_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(xyz.shape[0], min(ntgt, xyz.shape[0]), replace=False)
+    R = 1 if q.ndim == 1 else q.shape[1]
+    dense.potential(xyz[:64], q[:64], W.K_WAVENUMBER)   # load the library
+    t0 = time.perf_counter()
+    dense.potential(xyz, q, W.K_WAVENUMBER, tgt=xyz[idx])
+    dt = time.perf_counter() - t0
+    pairs = float(idx.size) * xyz.shape[0] * R
+    return {"pairs_per_s": round(pairs / dt, 1), "targets": int(idx.size),
+            "seconds": round(dt, 3),
+            "full_matvec_s_extrapolated": round(dt * xyz.shape[0] / idx.size, 2)}
+
+
+def cpu_baseline(xyz, q, phi_gpu, repeats=3):
+    """The FP64 oracle MLFMA, untuned, timed on the host cores: the median
+    of `repeats` full matvecs of the same workload (setup excluded), plus
+    the plain dense sum on 2,048 sampled targets."""
     from oracle import dense
     from oracle import mlfma as M
     from paper_2006_15367_amd import workloads as W
     tree = M.Tree(xyz, W.LEAF_SIZE)
     ops = M.Operators(tree, W.K_WAVENUMBER, W.DIGITS)
-    t0 = time.perf_counter()
-    phi = M.matvec(tree, ops, q)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        phi = M.matvec(tree, ops, q)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     R = 1 if q.ndim == 1 else q.shape[1]
     err = float(np.linalg.norm(phi_gpu - phi) / np.linalg.norm(phi))
     rng = np.random.default_rng(7)
@@ -179,11 +240,114 @@ def cpu_baseline(xyz, q, phi_gpu):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
+    import platform
+    cpu_model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(xyz.shape[0] * R / dt, 1), "unit": "points/s", "cores": cores,
             "kind": "oracle", "seconds": round(dt, 3),
-            "sample": "one full FP64 oracle MLFMA matvec of the same workload (numpy + C "
-                      "near field), setup excluded",
+            "seconds_each": [round(t, 3) for t in times], "cpu": cpu_model,
+            "sample": "median of %d full FP64 oracle MLFMA matvecs of the same workload "
+                      "(numpy + C near field), setup excluded" % repeats,
+            "dense": dense_baseline(xyz, q),
             "gpu_rel_l2_vs_oracle_mlfma": err, "gpu_rel_l2_vs_dense_1024_targets": err_dense}
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _dense_check(xyz, q, phi, ntgt=128, ncol=4):
+    """rel. L2 of a GPU result against the dense FP64 sum on sampled targets
+    (at most ncol right-hand sides)."""
+    from oracle import dense
+    from paper_2006_15367_amd import workloads as W
+    rng = np.random.default_rng(3)
+    idx = rng.choice(xyz.shape[0], ntgt, replace=False)
+    qq = q if q.ndim == 1 else q[:, :ncol]
+    pp = phi[idx] if phi.ndim == 1 else phi[idx, :ncol]
+    ref = dense.potential(xyz, np.ascontiguousarray(qq).astype(np.complex128),
+                          W.K_WAVENUMBER, tgt=xyz[idx])
+    return float(np.linalg.norm(pp - ref) / np.linalg.norm(ref))
+
+
+def extra_workloads(headline_ms, steps=5, warmup=2):
+    """The other benchmark configurations, timed in the same run (inputs
+    resident, default schedule): the elongated cloud with its tip cluster,
+    64 right-hand sides in FP32 and with BF16x3 interpolation, and the
+    volume cloud with 16 right-hand sides (matvec, and loss + backward of
+    ||phi - phi_target||^2 through the adjoint and field passes)."""
+    import gc
+    import torch
+    from paper_2006_15367_amd import mlfma as G
+    from paper_2006_15367_amd import workloads as W
+    from paper_2006_15367_amd.autograd import potential
+    out = {}
+    r64_fp32 = None
+    for key, name, bf in (("spheroid1m", "spheroid1m", False),
+                          ("sphere262k_r64", "sphere262k_r64", False),
+                          ("sphere262k_r64_bf16x3", "sphere262k_r64", True),
+                          ("cube1m_r16", "cube1m_r16", False)):
+        try:
+            xyz, q = W.make(name)
+            R = 1 if q.ndim == 1 else q.shape[1]
+            t0 = time.perf_counter()
+            tree = G.Tree(xyz, W.LEAF_SIZE)
+            ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=bf)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            qd = torch.from_numpy(np.ascontiguousarray(q.astype(np.complex64))).cuda()
+            ms = _timed(lambda: ops.matvec(qd), steps, warmup)
+            phi = ops.matvec(qd)
+            torch.cuda.synchronize()
+            e = {"n_points": int(xyz.shape[0]), "nrhs": R, "ms_per_matvec": round(ms, 3),
+                 "points_x_rhs_per_s": round(xyz.shape[0] * R / (ms * 1e-3), 1),
+                 "setup_s": round(setup, 2), "levels": tree.info()["n_levels"],
+                 "rel_l2_vs_dense_128_targets": _dense_check(xyz, q, phi.cpu().numpy())}
+            if R > 1:
+                e["ms_per_rhs"] = round(ms / R, 4)
+            if name == "sphere262k_r64":
+                # same cloud as the headline: batched against single-RHS calls
+                e["speedup_per_rhs_vs_single_rhs_headline"] = round(headline_ms * R / ms, 3)
+            if key == "sphere262k_r64":
+                r64_fp32 = ms
+            if key == "sphere262k_r64_bf16x3" and r64_fp32:
+                e["speedup_vs_fp32_r64"] = round(r64_fp32 / ms, 3)
+            if key == "cube1m_r16":
+                tq = torch.from_numpy(W.charges(xyz.shape[0], R, seed=1)).cuda()
+                with torch.no_grad():
+                    target = ops.matvec(tq)
+                xg = torch.from_numpy(xyz).cuda()
+
+                def step():
+                    qq = qd.clone().requires_grad_(True)
+                    xx = xg.clone().requires_grad_(True)
+                    L = (potential(qq, xx, ops) - target).abs().pow(2).sum()
+                    L.backward()
+                e["loss_backward_ms"] = round(_timed(step, steps, warmup), 3)
+                e["loss_backward"] = ("||phi - phi_t||^2, phi_t = A q_t (charges seed 1); "
+                                      "grads w.r.t. complex charges and positions")
+                del target, xg, tq
+            out[key] = e
+            del ops, tree, qd, phi
+        except Exception as ex:  # keep the headline line whatever happens here
+            out[key] = {"error": "%s: %s" % (type(ex).__name__, ex)}
+        gc.collect()
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -199,6 +363,8 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="every kernel on the caller's stream (no near/far overlap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (spheroid, 64 RHS, volume cloud)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -238,12 +404,14 @@ def main():
         for _ in range(args.warmup):
             phi = ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
-        # one profiled (eager) step, every kernel timed alone, picks the
-        # dominant kernel
-        ops.profile_begin(None, 4096, serial=True)
-        ops.matvec(qd, stream=st)
+        # ten profiled (eager) steps, every kernel timed alone: per-phase
+        # times and the dominant kernel
+        n_prof = 10
+        ops.profile_begin(None, 4096 * n_prof, serial=True)
+        for _ in range(n_prof):
+            ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
-        per_kernel = ops.profile_end()
+        per_kernel = {k: (v[0] / n_prof, v[1] // n_prof) for k, v in ops.profile_end().items()}
         dominant = max(per_kernel, key=lambda k: per_kernel[k][0])
         launches = per_kernel[dominant][1]
 
@@ -313,6 +481,8 @@ def main():
     rl["event_steps"] = ev_steps
     rl["alone"] = {k: alone[k] for k in ("achieved", "frac", "avg_launch_us", "ms_per_step")}
     rl["traffic"] = recorded_traffic(dominant, args.workload, R)
+    phases, floor_ms = phase_rooflines(work, {k: v[0] for k, v in per_kernel.items()},
+                                       args.bf16x3)
     if rl["traffic"] is not None:
         rl["algorithmic_bytes_per_launch"] = round(work[dominant]["bytes"] / max(1, launches), 1)
     value = xyz.shape[0] * R / (ms_per_step * 1e-3)
@@ -340,8 +510,15 @@ def main():
         "onepass_interp_per_level": ops.variants("interp"),
         "onepass_anterp_per_level": ops.variants("anterp"),
         "roofline": rl,
+        "phases": phases,
+        "whole_matvec": {"floor_ms": round(floor_ms, 5), "ms": round(ms_per_step, 4),
+                         "frac": round(floor_ms / ms_per_step, 4),
+                         "floor": "sum over phases of max(algorithmic bytes / 8 TB/s, "
+                                  "algorithmic flops / compute peak)"},
         "gmres": gmres,
     }
+    if not args.no_extras and args.workload == "sphere262k" and not args.graph:
+        out["extra_workloads"] = extra_workloads(ms_per_step)
     if not args.no_cpu_baseline:
         phi_np = phi.cpu().numpy().astype(np.complex128)
         out["cpu_baseline"] = cpu_baseline(xyz, q.astype(np.complex128), phi_np)

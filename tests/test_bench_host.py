@@ -63,3 +63,25 @@ def test_onepass_work_split_books_on_the_onepass_kernel():
         dn = sum(staged[k]["flops"] for k in ("anterp_s1", "anterp_s2", "anterp_s3"))
         assert w["interp"]["flops"] == up > 0
         assert w["anterp"]["flops"] == dn > 0
+
+
+def test_phase_rooflines_sum_the_kernels_of_each_phase():
+    """Each phase books the work and the time of its kernels; its floor is
+    the larger of the HBM and compute times at peak, and the whole-matvec
+    floor is the sum of the phase floors."""
+    tinfo, levels = _fake_levels()
+    work = bench.algorithmic_work(tinfo, levels, 1, [-1, -1, 0, -1], [-1, -1, 0, -1])
+    ms = {"p2p": 0.5, "interp_s1": 0.1, "interp_s2": 0.2, "interp_s3": 0.3, "m2l": 1.0}
+    ph, floor = bench.phase_rooflines(work, ms, False)
+    m2m_flops = sum(work[k]["flops"] for k in ("interp_s1", "interp_s2", "interp_s3"))
+    assert abs(ph["m2m"]["achieved"] - round(m2m_flops / 0.6e-3 / 1e12, 3)) < 1e-3
+    assert ph["m2m"]["bound"] == "mfma" and ph["p2p"]["bound"] == "alu"
+    assert "l2l" not in ph          # no time booked: not reported
+    expect = 0.0
+    for p, ks in bench.PHASES.items():
+        fl = sum(work[k]["flops"] for k in ks)
+        by = sum(work[k]["bytes"] for k in ks)
+        expect += max(by / 8e12, fl / 157.3e12) * 1e3
+    assert abs(floor - expect) < 1e-12
+    ph3, _ = bench.phase_rooflines(work, ms, True)
+    assert ph3["m2m"]["peak"] == bench.PEAK_BF16_TFLOPS
