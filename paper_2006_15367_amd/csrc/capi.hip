@@ -44,7 +44,8 @@ struct DevLevel {
     int m2l_variant = 0;             // 0 per-observer (L2), 1 operators in LDS, 2 sibling groups,
                                      // 3 sibling groups with per-source records, 4 = 3 with
                                      // the slice-major sweep, 5 = 3 record-balanced, 6 = 5 on
-                                     // 32-sample slices, 7 = 5 on antipodal slices
+                                     // 32-sample slices, 7 = 5 on antipodal slices, 8 = 5 on
+                                     // octant slices
     int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     // antipodal slices (one-RHS variant 7): operators of one offset of each
@@ -54,6 +55,15 @@ struct DevLevel {
     int32_t *aperm = nullptr, *rec_off_anti = nullptr;
     int ntp = 0;
     int64_t Kp = 0;
+    // octant slices (one-RHS variant 8): operators of the offsets
+    // (|dx|, |dy|, |dz|) in slice-lane order [nto][Ko], slot codes [Ko]
+    // (sample, or -(sample + 2) for a repeated direction, -1 padding), and
+    // the record slots as row * 512 | 8 g (g: reflections x, y, z as bits
+    // 2, 1, 0)
+    float2 *To = nullptr;
+    int32_t *operm = nullptr, *rec_off_oct = nullptr;
+    int nto = 0;
+    int64_t Ko = 0;
     float2 *S = nullptr, *Lloc = nullptr;  // [nbox][R][K]
     int Lc = 0, Mc = 0;
     float2 *shift = nullptr, *shift_axis = nullptr;
@@ -310,6 +320,12 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
                                  D.rec_off_anti, D.Tp, D.aperm, D.Kp, D.S, D.Lloc, s, max_wg);
         return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
                             D.rec_off, D.T, D.S, R, D.Lloc, s, 2, max_wg);
+    case 8:
+        if (R == 1)
+            return dev::m2l_anti(Pl.nbox, D.K, D.nto, Pl.child_start, D.rec_start, D.rec_src,
+                                 D.rec_off_oct, D.To, D.operm, D.Ko, D.S, D.Lloc, s, max_wg, 8);
+        return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
+                            D.rec_off, D.T, D.S, R, D.Lloc, s, 2, max_wg);
     case 3:
     case 4:
     case 5:
@@ -397,8 +413,8 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < 8; ++v) {
-            if (v >= 6 && R != 1) continue;  // variants 6 and 7 serve one RHS
+        for (int v = 0; v < 9; ++v) {
+            if (v >= 6 && R != 1) continue;  // variants 6, 7 and 8 serve one RHS
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -810,6 +826,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             pl.add((int64_t)H.far_src.size() * 36 + (H.nbox + 1) * 4);  // M2L records (bound)
             pl.add((int64_t)H.far_src.size() * 32);                     // antipodal record slots
             pl.add(((int64_t)T.ntypes + 1) * (T.K / 2 + 64) * 8 + (T.K + 64) * 4);  // Tp, aperm
+            pl.add((int64_t)H.far_src.size() * 32);                     // octant record slots
+            pl.add(57 * (8 * T.K + 64) * 8 + (8 * T.K + 64) * 4);       // To, operm (bound)
             pl.add(H.nbox * R * T.K * 8 * 2);
             if (l < nl) {
                 const LevelTables &C = o->tab[l + 1];
@@ -1022,6 +1040,79 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 if ((r = upload(o, &D.Tp, tpv.data(), (int64_t)tpv.size()))) return r;
                 if ((r = upload(o, &D.aperm, ap.data(), D.Kp))) return r;
                 if ((r = upload(o, &D.rec_off_anti, ranti.data(), (int64_t)ranti.size()))) return r;
+
+                // octant slices: reflection g (bit 2: x, phi -> pi - phi;
+                // bit 1: y, phi -> -phi; bit 0: z, theta -> pi - theta) of
+                // sample q; the reflected offset R_g d has T_{R_g d}(q) =
+                // T_d(refl(g, q))
+                auto refl = [&](int g, int64_t q) -> int64_t {
+                    int64_t i = q / T.nph, j = q % T.nph;
+                    if (g & 1) i = T.nth - 1 - i;
+                    if (g & 2) j = (T.nph - j) % T.nph;
+                    if (g & 4) j = (T.nph / 2 - j + T.nph) % T.nph;
+                    return i * T.nph + j;
+                };
+                std::vector<char> seen((size_t)K, 0);
+                std::vector<int64_t> orbit0;
+                for (int64_t q = 0; q < K; ++q) {
+                    if (seen[(size_t)q]) continue;
+                    orbit0.push_back(q);
+                    for (int g = 0; g < 8; ++g) seen[(size_t)refl(g, q)] = 1;
+                }
+                const int64_t nso = ((int64_t)orbit0.size() + 7) / 8;
+                D.Ko = nso * 64;
+                std::vector<int32_t> opm((size_t)D.Ko, -1);
+                for (size_t ob = 0; ob < orbit0.size(); ++ob)
+                    for (int g = 0; g < 8; ++g) {
+                        const int64_t q = refl(g, orbit0[ob]);
+                        bool first = true;
+                        for (int h = 0; h < g; ++h)
+                            if (refl(h, orbit0[ob]) == q) first = false;
+                        opm[ob * 8 + g] = first ? (int32_t)q : (int32_t)(-q - 2);
+                    }
+                // rows: the offsets (|dx|, |dy|, |dz|) of the used offsets
+                std::vector<int> row_of(64, -1), src_code(64, -1);
+                int nto = 0;
+                for (int c = 0; c < 343; ++c) {
+                    if (T.code_to_type[c] < 0) continue;
+                    const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+                    const int a = std::abs(dx) * 16 + std::abs(dy) * 4 + std::abs(dz);
+                    if (row_of[a] < 0) {
+                        row_of[a] = nto++;
+                        src_code[a] = c;
+                    }
+                }
+                D.nto = nto;
+                std::vector<float2> tov((size_t)nto * D.Ko, make_float2(0.f, 0.f));
+                for (int a = 0; a < 64; ++a) {
+                    if (row_of[a] < 0) continue;
+                    const int c = src_code[a];
+                    const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+                    const int g = (dx < 0 ? 4 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 1 : 0);
+                    const int t = T.code_to_type[c];
+                    // T_{|d|}(q) = T_{R_g |d|}(refl(g, q)), R_g |d| = d
+                    for (int64_t e = 0; e < D.Ko; ++e) {
+                        const int32_t cd = opm[(size_t)e];
+                        if (cd == -1) continue;
+                        const int64_t q = cd >= 0 ? cd : -(int64_t)cd - 2;
+                        tov[(size_t)row_of[a] * D.Ko + e] = Th[(size_t)t * K + refl(g, q)];
+                    }
+                }
+                std::vector<int32_t> roct(roff.size());
+                for (size_t e = 0; e < roff.size(); ++e) {
+                    if (roff[e] == zero_row) {
+                        roct[e] = nto * 512;
+                        continue;
+                    }
+                    const int c = type_code[roff[e] / (64 * (int32_t)sizeof(float2))];
+                    const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+                    const int a = std::abs(dx) * 16 + std::abs(dy) * 4 + std::abs(dz);
+                    const int g = (dx < 0 ? 4 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 1 : 0);
+                    roct[e] = row_of[a] * 512 | (g * 8);
+                }
+                if ((r = upload(o, &D.To, tov.data(), (int64_t)tov.size()))) return r;
+                if ((r = upload(o, &D.operm, opm.data(), D.Ko))) return r;
+                if ((r = upload(o, &D.rec_off_oct, roct.data(), (int64_t)roct.size()))) return r;
             }
             {
                 std::vector<int32_t> bs(H.nbox);
@@ -1577,7 +1668,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-        if (variant < 0 || variant > 7) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (variant < 0 || variant > 8) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
         o->lev[level].m2l_variant = variant;
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)

@@ -115,7 +115,7 @@ int cu_count();
 hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_start,
                     const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                     const float2 *Tp, const int32_t *aperm, int64_t Kp, const float2 *S,
-                    float2 *Lout, hipStream_t s, int max_wg = 0);
+                    float2 *Lout, hipStream_t s, int max_wg = 0, int waves = 16);
 
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,

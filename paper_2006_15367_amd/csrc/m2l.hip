@@ -737,6 +737,19 @@ k_m2l_rec_half(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict
 // value XOR (8 lane): the mirrored lane for a negated offset, at the cost
 // of the addition it replaces.  Parents are scheduled as in the balanced
 // schedule of k_m2l_rec.
+//
+// The same kernel runs octant slices (variant 8, 8-wave workgroups): the
+// reflection of an offset in any coordinate plane maps the operator to the
+// reflected directions, T_{R d}(k) = T_d(R k), and the grid is closed
+// under the three reflections (x: phi -> pi - phi, y: phi -> -phi, z:
+// theta -> pi - theta).  A slice holds 8 orbits of 8 directions, lane
+// 8 o + g carrying reflection g (3 bits) of orbit o's first direction, and
+// LDS the operators of the offsets (|dx|, |dy|, |dz|) only (at most 56 + 1
+// rows, 29 KB: several workgroups per CU).  A record slot holds
+// row * 512 | 8 g for the offset R_g (|d|), so the same XOR with 8 lane
+// lands on lane 8 o + (g' ^ g), the reflected direction.  A direction
+// fixed by some reflection appears more than once in its orbit; only its
+// first slot writes (slot codes below zero).
 template <int NW>
 __global__ void __launch_bounds__(64 * NW)
 k_m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *__restrict__ child_start,
@@ -758,11 +771,14 @@ k_m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *__restrict__ chil
     const char *Tsb = (const char *)Ts;
     const int lane = threadIdx.x & 63;
     const int lane8 = lane * 8;
-    const int k = aperm[k0 + lane];
-    const bool valid = k >= 0;
+    // slot code: sample q >= 0 (computed and written), -(q + 2) (computed,
+    // not written: a repeat of a sample earlier in the slice), -1 (padding)
+    const int code = aperm[k0 + lane];
+    const int k = code >= 0 ? code : (code <= -2 ? -code - 2 : 0);
+    const bool valid = code >= 0;
     // (a multiple of 8 below 2^31, as the mask states: the value's two
     // 32-bit loads merge into one)
-    const uint32_t voff = ((uint32_t)(valid ? k : 0) * (uint32_t)sizeof(float2)) & 0x7ffffff8u;
+    const uint32_t voff = ((uint32_t)k * (uint32_t)sizeof(float2)) & 0x7ffffff8u;
     const uint64_t sstride = (uint64_t)K * sizeof(float2);
     const char *Sb = (const char *)S;
     const int64_t total = rec_start[nparent];
@@ -809,24 +825,45 @@ k_m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *__restrict__ chil
     }
 }
 
+// Resident workgroups of k_m2l_anti<NW> per CU with `lds` bytes of dynamic
+// LDS (occupancy query, cached per (NW, lds) on the current device).
+template <int NW>
+static int anti_per_cu(size_t lds)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_m2l_anti<NW>, 64 * NW, lds) !=
+            hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = (int)std::max<size_t>(1, 163840 / (lds + 16));
+    }
+    return nb;
+}
+
 hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_start,
                     const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                     const float2 *Tp, const int32_t *aperm, int64_t Kp, const float2 *S,
-                    float2 *Lout, hipStream_t s, int max_wg)
+                    float2 *Lout, hipStream_t s, int max_wg, int waves)
 {
     if (nparent == 0 || K == 0) return hipSuccess;
     const size_t lds = (size_t)(ntp + 1) * 64 * sizeof(float2);
     if (lds + 16 > 163840) return hipErrorInvalidValue;  // + the static counter
     if ((uint64_t)K * sizeof(float2) > 0x7fffffffull || Kp % 64 != 0) return hipErrorInvalidValue;
-    const int NW = 16;
+    if (waves != 8 && waves != 16) return hipErrorInvalidValue;
     const int nkc = (int)(Kp / 64);
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, 163840 / (lds + 16)));
     const int ncu = max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count();
+    // antipodal slices (16 waves): at most two workgroups per CU; octant
+    // slices (8 waves, a quarter of the LDS): as many as fit
+    const int per_cu = waves == 16 ? std::min(2, anti_per_cu<16>(lds)) : anti_per_cu<8>(lds);
     const int nrange = (int)std::max<int64_t>(
-        1, std::min<int64_t>(per_cu * ncu / nkc, (nparent + NW - 1) / NW));
-    M2L_LAUNCH((k_m2l_anti<16>), dim3((unsigned)(nkc * nrange)), dim3(64 * NW), lds, s,
-                       nparent, K, ntp, child_start, rec_start, rec_src, rec_off, Tp, aperm, Kp,
-                       S, nkc, nrange, Lout);
+        1, std::min<int64_t>(per_cu * ncu / nkc, (nparent + waves - 1) / waves));
+    if (waves == 16)
+        M2L_LAUNCH((k_m2l_anti<16>), dim3((unsigned)(nkc * nrange)), dim3(64 * 16), lds, s,
+                   nparent, K, ntp, child_start, rec_start, rec_src, rec_off, Tp, aperm, Kp, S,
+                   nkc, nrange, Lout);
+    else
+        M2L_LAUNCH((k_m2l_anti<8>), dim3((unsigned)(nkc * nrange)), dim3(64 * 8), lds, s,
+                   nparent, K, ntp, child_start, rec_start, rec_src, rec_off, Tp, aperm, Kp, S,
+                   nkc, nrange, Lout);
     return hipGetLastError();
 }
 

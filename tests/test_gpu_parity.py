@@ -142,7 +142,7 @@ def test_field_vs_dense(c1):
     assert e < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_every_m2l_variant(c1, variant):
     torch = c1["torch"]
     say("c1: M2L variant", variant)
@@ -340,7 +340,7 @@ def test_variant_and_schedule_limits(c1):
     nl = c1["ot"].n_lev
     before = (ops.variants("m2l"), ops.variants("p2p"))
     bad = [
-        (3, 8, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
+        (3, 9, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
         (0, 3, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
         (nl, 0, "interp"),
     ]
