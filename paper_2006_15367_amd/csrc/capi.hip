@@ -25,6 +25,9 @@ namespace {
 
 std::atomic<int64_t> g_mem_limit{0};
 
+// interpolation / anterpolation variant value of the fused pair kernel
+constexpr int kPairVariant = 4;
+
 struct DevLevel {
     int64_t nbox = 0;
     int L = 0, nth = 0, nph = 0;
@@ -69,9 +72,16 @@ struct DevLevel {
     float2 *shift = nullptr, *shift_axis = nullptr;
     float *iF = nullptr, *iA = nullptr, *iG = nullptr;
     float *aF = nullptr, *aB = nullptr, *aG = nullptr;
-    // level pair (this level = parent): 0 three passes through HBM, 1 one pass
+    // level pair (this level = parent): 0 three passes through HBM, 1 + k
+    // one pass in work split k, 4 the fused pair kernel
     int interp_variant = 0, anterp_variant = 0;
     bool onepass_ok = false;         // the one-pass kernels fit in LDS
+    // fused pair kernel: parent groups (first, one past last) and operator
+    // fragment tables of each direction
+    bool pair_ok = false;
+    int4 *ptile[2] = {nullptr, nullptr};
+    int64_t nptile[2] = {0, 0};
+    float *pfr[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
 };
 
 }  // namespace
@@ -337,6 +347,15 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
     }
 }
 
+// Fused pair kernel of the level pair (l, l+1): M2M (down = 0) or L2L.
+hipError_t launch_pair(mlfma_ops_s *o, int l, int R, hipStream_t s, int down)
+{
+    DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+    return dev::pair_map(C.L, P.L, down != 0, down ? P.Lloc : C.S, down ? C.Lloc : P.S,
+                         P.ptile[down], P.nptile[down], R, P.pfr[down][0], P.pfr[down][1],
+                         P.pfr[down][2], P.shift_axis, P.shift, s);
+}
+
 // One-pass interpolation / anterpolation of the level pair (l, l+1).
 hipError_t launch_interp_onepass(mlfma_ops_s *o, int l, int R, hipStream_t s, int shape)
 {
@@ -430,7 +449,7 @@ int autotune(mlfma_ops_s *o)
     const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
     for (int l = 3; l < o->n_lev && rc == MLFMA_OK; ++l) {
         DevLevel &P = o->lev[l];
-        if (!P.onepass_ok || b3) continue;
+        if (!(P.onepass_ok || P.pair_ok) || b3) continue;
         // variant 0: three passes; 1 + k: one pass in work split k
         float bi = time_best(s, e0, e1, [&] { return launch_interp_staged(o, l, R, s); });
         float ba = time_best(s, e0, e1, [&] { return launch_anterp_staged(o, l, R, s); });
@@ -439,7 +458,23 @@ int autotune(mlfma_ops_s *o)
             break;
         }
         P.interp_variant = P.anterp_variant = 0;
-        const int nsh = dev::pair_onepass_shapes(o->lev[l + 1].L, P.L);
+        if (P.pair_ok) {
+            const float tf = time_best(s, e0, e1, [&] { return launch_pair(o, l, R, s, 0); });
+            const float af = time_best(s, e0, e1, [&] { return launch_pair(o, l, R, s, 1); });
+            if (tf < 0.f || af < 0.f) {
+                rc = fail(MLFMA_EDEVICE, "autotune: pair kernel failed on level %d", l);
+                break;
+            }
+            if (tf < bi) {
+                bi = tf;
+                P.interp_variant = kPairVariant;
+            }
+            if (af < ba) {
+                ba = af;
+                P.anterp_variant = kPairVariant;
+            }
+        }
+        const int nsh = P.onepass_ok ? dev::pair_onepass_shapes(o->lev[l + 1].L, P.L) : 0;
         for (int k = 0; k < nsh && rc == MLFMA_OK; ++k) {
             const float tf = time_best(s, e0, e1, [&] { return launch_interp_onepass(o, l, R, s, k); });
             const float af = time_best(s, e0, e1, [&] { return launch_anterp_onepass(o, l, R, s, k); });
@@ -504,7 +539,9 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
-        if (P.interp_variant >= 1) {
+        if (P.interp_variant == kPairVariant) {
+            LAUNCH(MLFMA_K_INTERP, launch_pair(o, l, R, s, 0));
+        } else if (P.interp_variant >= 1) {
             LAUNCH(MLFMA_K_INTERP, launch_interp_onepass(o, l, R, s, P.interp_variant - 1));
         } else {
             LAUNCH(MLFMA_K_INTERP_S1, dev::interp_s1(C.S, C.nbox * R, C.nth, C.nph, P.iF, M, o->X1, s, b3));
@@ -526,6 +563,10 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     for (int l = 3; l < nl; ++l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
+        if (P.anterp_variant == kPairVariant) {
+            LAUNCH(MLFMA_K_ANTERP, launch_pair(o, l, R, s, 1));
+            continue;
+        }
         if (P.anterp_variant >= 1) {
             LAUNCH(MLFMA_K_ANTERP, launch_anterp_onepass(o, l, R, s, P.anterp_variant - 1));
             continue;
@@ -835,6 +876,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 pl.add((int64_t)T.shift_axis.size() * 4);
                 pl.add(((int64_t)T.iF.size() + T.iA.size() + T.iG.size() + T.aF.size() +
                         T.aB.size() + T.aG.size()) * 4);
+                pl.add(2 * (H.nbox + 1) * 8 + 2 * 4 * ((int64_t)T.iF.size() + T.iA.size() +
+                                                      T.iG.size() + 64 * 64));  // pair kernel
                 const int64_t e = t->lev[l + 1].nbox * R * std::max(C.nth, T.nth) * T.Mc;
                 scratch = std::max(scratch, e);
             }
@@ -1153,6 +1196,51 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             const bool use = P.onepass_ok && !(flags & MLFMA_BF16X3_INTERP);
             P.interp_variant = use ? 1 : 0;
             P.anterp_variant = use ? 1 : 0;
+        }
+        // fused pair kernel (FP32 path): parent groups and fragment tables
+        for (int l = 3; l < nl && !(flags & MLFMA_BF16X3_INTERP); ++l) {
+            DevLevel &P = o->lev[l], &C = o->lev[l + 1];
+            if (!dev::pair_kernel_fits(C.L, P.L)) continue;
+            const LevelTables &T = o->tab[l];
+            const HostLevel &H = t->lev[l];
+            for (int dn = 0; dn < 2; ++dn) {
+                dev::PairTables pt;
+                if (dev::pair_tables(C.L, P.L, dn == 1, dn ? T.aF.data() : T.iF.data(),
+                                     dn ? T.aB.data() : T.iA.data(),
+                                     dn ? T.aG.data() : T.iG.data(), &pt))
+                    return fail(MLFMA_EINVAL, "precompute: pair tables of level %d", l);
+                // runs of whole parents with at most max_children (8)
+                // children, each described by two int4 (see pair_map)
+                const HostLevel &HC = t->lev[l + 1];
+                std::vector<int4> tiles;
+                for (int64_t p = 0; p < H.nbox;) {
+                    int64_t q = p;
+                    while (q < H.nbox && q - p < pt.max_parents &&
+                           H.child_start[q + 1] - H.child_start[p] <= pt.max_children)
+                        ++q;
+                    const int cb = H.child_start[p], nb = H.child_start[q] - cb;
+                    int octs = 0, ppf = 0, spar = 0;
+                    for (int i = 0; i < nb; ++i) {
+                        const int32_t *cc = &HC.coord[3 * (cb + i)];
+                        const int oc = ((cc[0] & 1) << 2) | ((cc[1] & 1) << 1) | (cc[2] & 1);
+                        octs |= oc << (3 * i);
+                    }
+                    for (int64_t j = 1; j < q - p; ++j)
+                        ppf |= (H.child_start[p + j] - cb) << (4 * (j - 1));
+                    for (int64_t j = 0; j < q - p; ++j)
+                        for (int i = H.child_start[p + j] - cb; i < H.child_start[p + j + 1] - cb; ++i)
+                            spar |= (int)j << (3 * i);
+                    tiles.push_back(make_int4((int)p, cb, nb, (int)(q - p)));
+                    tiles.push_back(make_int4(octs, ppf, spar, 0));
+                    p = q;
+                }
+                P.nptile[dn] = (int64_t)tiles.size() / 2;
+                if ((r = upload(o, &P.ptile[dn], tiles.data(), (int64_t)tiles.size()))) return r;
+                if ((r = upload(o, &P.pfr[dn][0], pt.fr1.data(), (int64_t)pt.fr1.size()))) return r;
+                if ((r = upload(o, &P.pfr[dn][1], pt.fr2.data(), (int64_t)pt.fr2.size()))) return r;
+                if ((r = upload(o, &P.pfr[dn][2], pt.fr3.data(), (int64_t)pt.fr3.size()))) return r;
+            }
+            P.pair_ok = true;
         }
         if (!(flags & MLFMA_NO_AUTOTUNE)) {
             if ((r = autotune(o))) return r;
@@ -1674,11 +1762,17 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
         if (level < 3 || level >= o->n_lev)
             return fail(MLFMA_EINVAL, "ops_set_variant: bad level pair %d", level);
         const int nsh = dev::pair_onepass_shapes(o->lev[level + 1].L, o->lev[level].L);
-        if (variant < 0 || variant > std::max(1, nsh))
-            return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
-        if (variant >= 1 && (!o->lev[level].onepass_ok || (o->flags & MLFMA_BF16X3_INTERP)))
-            return fail(MLFMA_EINVAL, "ops_set_variant: one-pass kernel unavailable on level pair %d",
-                        level);
+        if (variant == kPairVariant) {
+            if (!o->lev[level].pair_ok)
+                return fail(MLFMA_EINVAL, "ops_set_variant: pair kernel unavailable on level pair %d",
+                            level);
+        } else {
+            if (variant < 0 || variant > std::max(1, nsh))
+                return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+            if (variant >= 1 && (!o->lev[level].onepass_ok || (o->flags & MLFMA_BF16X3_INTERP)))
+                return fail(MLFMA_EINVAL,
+                            "ops_set_variant: one-pass kernel unavailable on level pair %d", level);
+        }
         (kernel == MLFMA_K_INTERP ? o->lev[level].interp_variant : o->lev[level].anterp_variant) =
             variant;
     } else if (kernel == MLFMA_K_P2P) {

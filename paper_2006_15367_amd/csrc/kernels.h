@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace mlfma {
 namespace dev {
@@ -65,6 +66,26 @@ hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
 // F [nphi_in][M], A [(M+1)/2][ntheta_in][ntheta_out], G [M][nphi_out];
 // E3: the axis factors of the shift on the parent grid.
 // shape: the work split, 0 .. pair_onepass_shapes(Lc, Lp) - 1.
+// Fused level-pair map (pair.hip): the three maps, the shift and the
+// sibling sum (M2M, written to the parent) or the add into the child's
+// local (L2L) in one launch over tiles of whole parents.  Instantiated
+// pairs only (pair_kernel_fits).  pair_tables builds the operator
+// fragment tables on the host from the pair's maps (M2M: iF, iA, iG; L2L:
+// aF, aB, aG) and states the tile limit (children per tile, whole parents);
+// desc[2g], desc[2g + 1] describe group g: (first parent, first child,
+// children, parents) and (octant of child slot i at bits 3i, first slot of
+// parent j = 1..7 at bits 4(j - 1), parent of slot i at bits 3i, 0).
+struct PairTables {
+    std::vector<float> fr1, fr2, fr3;
+    int max_children = 0, max_parents = 0;
+};
+bool pair_kernel_fits(int Lc, int Lp);
+int pair_tables(int Lc, int Lp, bool down, const float *F, const float *A, const float *G,
+                PairTables *t);
+hipError_t pair_map(int Lc, int Lp, bool down, const float2 *In, float2 *Out, const int4 *desc,
+                    int64_t ngroups, int R, const float *fr1, const float *fr2, const float *fr3,
+                    const float2 *shift_axis, const float2 *shift, hipStream_t st);
+
 bool pair_onepass_fits(int Lc, int Lp);
 int pair_onepass_shapes(int Lc, int Lp);
 hipError_t interp_fused(int64_t nboxp, int R, int Lc, int Lp, int shape,

@@ -156,11 +156,12 @@ def test_deep_every_m2l_form_on_every_level(c2, variant):
     assert rel_l2(P[:, 0], phi) < 1e-5
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_deep_every_interpolation_form(c2, variant):
-    """Three passes (0) or one pass in work split variant - 1, forced on
-    every level pair that has that form (the one-pass kernels exist for the
-    two finest pairs); the other pairs keep the autotuner's choice."""
+    """Three passes (0), one pass in work split variant - 1 (1..3) or the
+    fused pair kernel (4), forced on every level pair that has that form
+    (the one-pass and pair kernels exist for the two finest pairs); the
+    other pairs keep the autotuner's choice."""
     G = c2["G"]
     ops = c2["gops"]
     nl = c2["ot"].n_lev

@@ -172,10 +172,11 @@ def test_every_m2l_variant(c1, variant):
     assert rel_l2(P[:, 0], phi) < 1e-5
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_interpolation_variants(c1, variant):
-    """Three-pass (0) and one-pass (1 + work split) M2M / L2L: per-level
-    multipoles and locals against the oracle, then end to end."""
+    """Three-pass (0), one-pass (1 + work split) and fused pair kernel (4)
+    M2M / L2L: per-level multipoles and locals against the oracle, then end
+    to end."""
     torch = c1["torch"]
     say("c1: interpolation variant", variant)
     qd = torch.from_numpy(c1["q"].astype(np.complex64)).cuda()
