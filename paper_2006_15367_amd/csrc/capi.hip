@@ -78,7 +78,7 @@ struct DevLevel {
     bool onepass_ok = false;         // the one-pass kernels fit in LDS
     // fused pair kernel: parent groups (first, one past last) and operator
     // fragment tables of each direction
-    bool pair_ok = false;
+    bool pair_ok[2] = {false, false};
     int4 *ptile[2] = {nullptr, nullptr};
     int64_t nptile[2] = {0, 0};
     float *pfr[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
@@ -449,7 +449,7 @@ int autotune(mlfma_ops_s *o)
     const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
     for (int l = 3; l < o->n_lev && rc == MLFMA_OK; ++l) {
         DevLevel &P = o->lev[l];
-        if (!(P.onepass_ok || P.pair_ok) || b3) continue;
+        if (!(P.onepass_ok || P.pair_ok[0] || P.pair_ok[1]) || b3) continue;
         // variant 0: three passes; 1 + k: one pass in work split k
         float bi = time_best(s, e0, e1, [&] { return launch_interp_staged(o, l, R, s); });
         float ba = time_best(s, e0, e1, [&] { return launch_anterp_staged(o, l, R, s); });
@@ -458,22 +458,20 @@ int autotune(mlfma_ops_s *o)
             break;
         }
         P.interp_variant = P.anterp_variant = 0;
-        if (P.pair_ok) {
-            const float tf = time_best(s, e0, e1, [&] { return launch_pair(o, l, R, s, 0); });
-            const float af = time_best(s, e0, e1, [&] { return launch_pair(o, l, R, s, 1); });
-            if (tf < 0.f || af < 0.f) {
+        for (int dn = 0; dn < 2 && rc == MLFMA_OK; ++dn) {
+            if (!P.pair_ok[dn]) continue;
+            const float tp = time_best(s, e0, e1, [&] { return launch_pair(o, l, R, s, dn); });
+            if (tp < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: pair kernel failed on level %d", l);
                 break;
             }
-            if (tf < bi) {
-                bi = tf;
-                P.interp_variant = kPairVariant;
-            }
-            if (af < ba) {
-                ba = af;
-                P.anterp_variant = kPairVariant;
+            float &best = dn ? ba : bi;
+            if (tp < best) {
+                best = tp;
+                (dn ? P.anterp_variant : P.interp_variant) = kPairVariant;
             }
         }
+        if (rc != MLFMA_OK) break;
         const int nsh = P.onepass_ok ? dev::pair_onepass_shapes(o->lev[l + 1].L, P.L) : 0;
         for (int k = 0; k < nsh && rc == MLFMA_OK; ++k) {
             const float tf = time_best(s, e0, e1, [&] { return launch_interp_onepass(o, l, R, s, k); });
@@ -1200,10 +1198,10 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
         // fused pair kernel (FP32 path): parent groups and fragment tables
         for (int l = 3; l < nl && !(flags & MLFMA_BF16X3_INTERP); ++l) {
             DevLevel &P = o->lev[l], &C = o->lev[l + 1];
-            if (!dev::pair_kernel_fits(C.L, P.L)) continue;
             const LevelTables &T = o->tab[l];
             const HostLevel &H = t->lev[l];
             for (int dn = 0; dn < 2; ++dn) {
+                if (!dev::pair_kernel_fits(C.L, P.L, dn == 1)) continue;
                 dev::PairTables pt;
                 if (dev::pair_tables(C.L, P.L, dn == 1, dn ? T.aF.data() : T.iF.data(),
                                      dn ? T.aB.data() : T.iA.data(),
@@ -1239,8 +1237,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 if ((r = upload(o, &P.pfr[dn][0], pt.fr1.data(), (int64_t)pt.fr1.size()))) return r;
                 if ((r = upload(o, &P.pfr[dn][1], pt.fr2.data(), (int64_t)pt.fr2.size()))) return r;
                 if ((r = upload(o, &P.pfr[dn][2], pt.fr3.data(), (int64_t)pt.fr3.size()))) return r;
+                P.pair_ok[dn] = true;
             }
-            P.pair_ok = true;
         }
         if (!(flags & MLFMA_NO_AUTOTUNE)) {
             if ((r = autotune(o))) return r;
@@ -1763,7 +1761,7 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
             return fail(MLFMA_EINVAL, "ops_set_variant: bad level pair %d", level);
         const int nsh = dev::pair_onepass_shapes(o->lev[level + 1].L, o->lev[level].L);
         if (variant == kPairVariant) {
-            if (!o->lev[level].pair_ok)
+            if (!o->lev[level].pair_ok[kernel == MLFMA_K_INTERP ? 0 : 1])
                 return fail(MLFMA_EINVAL, "ops_set_variant: pair kernel unavailable on level pair %d",
                             level);
         } else {

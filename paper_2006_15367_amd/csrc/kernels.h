@@ -69,7 +69,7 @@ hipError_t anterp_s3(int64_t nboxc, int R, int nthc, int nphc, int M,
 // Fused level-pair map (pair.hip): the three maps, the shift and the
 // sibling sum (M2M, written to the parent) or the add into the child's
 // local (L2L) in one launch over tiles of whole parents.  Instantiated
-// pairs only (pair_kernel_fits).  pair_tables builds the operator
+// pairs and directions only (pair_kernel_fits).  pair_tables builds the operator
 // fragment tables on the host from the pair's maps (M2M: iF, iA, iG; L2L:
 // aF, aB, aG) and states the tile limit (children per tile, whole parents);
 // desc[2g], desc[2g + 1] describe group g: (first parent, first child,
@@ -79,7 +79,7 @@ struct PairTables {
     std::vector<float> fr1, fr2, fr3;
     int max_children = 0, max_parents = 0;
 };
-bool pair_kernel_fits(int Lc, int Lp);
+bool pair_kernel_fits(int Lc, int Lp, bool down);
 int pair_tables(int Lc, int Lp, bool down, const float *F, const float *A, const float *G,
                 PairTables *t);
 hipError_t pair_map(int Lc, int Lp, bool down, const float2 *In, float2 *Out, const int4 *desc,

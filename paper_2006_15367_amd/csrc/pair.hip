@@ -453,8 +453,9 @@ void fill_fragments(const float *F, const float *A, const float *G, PairTables *
 
 }  // namespace
 
-bool pair_kernel_fits(int Lc, int Lp)
+bool pair_kernel_fits(int Lc, int Lp, bool down)
 {
+    (void)down;  // both directions of the instantiated pairs
     return (Lc == 8 && Lp == 13) || (Lc == 13 && Lp == 20);
 }
 

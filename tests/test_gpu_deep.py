@@ -159,9 +159,10 @@ def test_deep_every_m2l_form_on_every_level(c2, variant):
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_deep_every_interpolation_form(c2, variant):
     """Three passes (0), one pass in work split variant - 1 (1..3) or the
-    fused pair kernel (4), forced on every level pair that has that form
-    (the one-pass and pair kernels exist for the two finest pairs); the
-    other pairs keep the autotuner's choice."""
+    fused pair kernel (4), forced on every level pair and direction that
+    has that form (the one-pass kernels exist for the two finest pairs, the
+    pair kernel for those and for the M2M of 20 -> 33); the others keep the
+    autotuner's choice."""
     G = c2["G"]
     ops = c2["gops"]
     nl = c2["ot"].n_lev
@@ -169,15 +170,13 @@ def test_deep_every_interpolation_form(c2, variant):
     forced = []
     try:
         for l in range(3, nl):
-            try:
-                for k in ("interp", "anterp"):
+            for k in ("interp", "anterp"):
+                try:
                     ops.set_variant(l, variant, kernel=k)
-                forced.append(l)
-            except G.MlfmaError as e:
-                assert e.status == G.EINVAL
-                for k in ("interp", "anterp"):
-                    ops.set_variant(l, chosen[k][l - 1], kernel=k)
-        say("deep: interpolation form", variant, "on level pairs", forced)
+                    forced.append((l, k))
+                except G.MlfmaError as e:
+                    assert e.status == G.EINVAL
+        say("deep: interpolation form", variant, "on (level pair, direction)", forced)
         if not forced:
             pytest.skip("no level pair has interpolation form %d" % variant)
         phi = _matvec(c2, c2["q"])
@@ -188,7 +187,7 @@ def test_deep_every_interpolation_form(c2, variant):
                 ops.set_variant(l, chosen[k][l - 1], kernel=k)
     assert rel_l2(phi, c2["ophi"]) < TOL_L
     if variant == 0:
-        assert forced == list(range(3, nl))
+        assert forced == [(l, k) for l in range(3, nl) for k in ("interp", "anterp")]
 
 
 def test_deep_bf16x3_levels(c2):
