@@ -350,6 +350,74 @@ def extra_workloads(headline_ms, steps=5, warmup=2):
     return out
 
 
+def smooth_phi_count(L):
+    """Smallest even phi count >= 2 L + 2 with no prime factor above 7 (the
+    uniform grids of the FFT interpolation)."""
+    P = 2 * L + 2
+    while True:
+        m = P
+        for r in (2, 3, 5, 7):
+            while m % r == 0:
+                m //= r
+        if m == 1 and P % 2 == 0:
+            return P
+        P += 1
+
+
+def fft_ablation(levels, nrhs, dense_phases, reps=20):
+    """The FFT interpolation (Sec. 3.2.2, Fig. 3) and its weighted-adjoint
+    anterpolation on uniform grids, timed on every level pair of the
+    workload with one item per child box and right-hand side, beside the
+    dense MFMA maps of the matvec (M2M and L2L phases alone, which also
+    shift and aggregate).  Algorithmic bytes: each item's input and output
+    grid once."""
+    import torch
+    from paper_2006_15367_amd import mlfma as G
+    lv = {e["level"]: e for e in levels if e["L"] > 0}
+    out = {"pairs": [], "grid": "uniform: P phi x P/2 theta samples, P = smallest 7-smooth "
+                                "even >= 2L + 2"}
+    tot = {False: 0.0, True: 0.0}
+    byt = {False: 0.0, True: 0.0}
+    for l in sorted(lv):
+        if l + 1 not in lv:
+            continue
+        Lc, Lp = lv[l + 1]["L"], lv[l]["L"]
+        Pc, Pp = smooth_phi_count(Lc), smooth_phi_count(Lp)
+        n = int(lv[l + 1]["nbox"]) * nrhs
+        e = {"child_L": Lc, "parent_L": Lp, "P_child": Pc, "P_parent": Pp, "items": n}
+        for ant in (False, True):
+            pi, po = (Pp, Pc) if ant else (Pc, Pp)
+            r = G.FFTResampler(Lc, pi, po, anterpolate=ant)
+            x = torch.randn(n, pi // 2, pi, dtype=torch.complex64, device="cuda")
+            y = r(x)
+            for _ in range(3):
+                r(x, out=y)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                r(x, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            b = 8.0 * n * (pi // 2 * pi + po // 2 * po)
+            key = "anterp" if ant else "interp"
+            e[key + "_ms"] = round(ms, 4)
+            e[key + "_GBs"] = round(b / (ms * 1e-3) / 1e9, 1)
+            tot[ant] += ms
+            byt[ant] += b
+            del x, y, r
+        out["pairs"].append(e)
+    for ant, key in ((False, "interp"), (True, "anterp")):
+        out[key + "_ms_total"] = round(tot[ant], 4)
+        gbs = byt[ant] / max(tot[ant] * 1e-3, 1e-12) / 1e9
+        out[key + "_hbm_frac"] = round(gbs / PEAK_HBM_GBS, 4)
+    out["dense_m2m_ms_alone"] = dense_phases.get("m2m", {}).get("ms_alone")
+    out["dense_l2l_ms_alone"] = dense_phases.get("l2l", {}).get("ms_alone")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,6 +585,12 @@ def main():
                                   "algorithmic flops / compute peak)"},
         "gmres": gmres,
     }
+    if not args.no_extras and args.workload in ("sphere262k", "sphere262k_r64") and \
+            not args.graph and not args.bf16x3:
+        try:
+            out["fft_interpolation"] = fft_ablation(levels, R, phases)
+        except Exception as ex:  # keep the headline line whatever happens here
+            out["fft_interpolation"] = {"error": "%s: %s" % (type(ex).__name__, ex)}
     if not args.no_extras and args.workload == "sphere262k" and not args.graph:
         out["extra_workloads"] = extra_workloads(ms_per_step)
     if not args.no_cpu_baseline:

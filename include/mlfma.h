@@ -292,6 +292,52 @@ int mlfma_solve_gmres_noalloc(mlfma_ops_t ops, const void *b, void *x, double sh
 void mlfma_destroy_ops(mlfma_ops_t ops);
 void mlfma_destroy_tree(mlfma_tree_t t);
 
+/*
+ * FFT interpolation / anterpolation between uniform sphere grids: the
+ * paper's M2M interpolation (Sec. 3.2.2, paragraph "Fine-grained Parallel
+ * Interpolation", Fig. 3: FFT interpolation along phi, then theta folded
+ * into whole circles and FFT-interpolated along them) and the reverse used
+ * in L2L (Sec. 3.2.4), as a batched operator, independent of any tree.
+ *
+ * Grid of P phi samples (P even): phi_j = 2 pi j / P, j < P, and P / 2
+ * theta samples theta_i = (i + 1/2) 2 pi / P (no poles), stored row-major
+ * [theta][phi] as complex64.  Interpolation maps the samples of a function
+ * of degree <= lband on the input grid to its samples on the output grid
+ * (exact up to FP32 rounding).  Anterpolation (anterpolate != 0) is the
+ * weighted adjoint of the interpolation from the output grid to the input
+ * grid, W_out^-1 I^T W_in, with W the quadrature weights (Fejer's first
+ * rule in theta times 2 pi / P): the anterpolated samples integrate against
+ * every function of degree <= lband as the input samples do.
+ *
+ * mlfma_fft_plan validates the sizes and prepares a plan on `device`:
+ *   lband      band limit (>= 0).
+ *   nphi_in, nphi_out  phi counts of the input and output grids: even,
+ *              2 lband + 2 <= P <= 1024, no prime factor above 7, and one
+ *              item's two LDS regions (2 x 8 x the largest intermediate
+ *              array) within 160 KiB (up to P = 120 both ways).
+ *   out        receives the plan (owned by the caller; mlfma_fft_destroy).
+ * Errors: MLFMA_EINVAL (sizes; no device call is made then), MLFMA_ENOMEM,
+ * MLFMA_EDEVICE.
+ *
+ * mlfma_fft_execute enqueues one kernel on `stream` (a hipStream_t, NULL =
+ * null stream) on the plan's device:
+ *   in         device, [nitems][nphi_in / 2][nphi_in] complex64.
+ *   out        device, [nitems][nphi_out / 2][nphi_out] complex64; must not
+ *              overlap `in`.
+ *   nitems     number of grids (boxes x right-hand sides); 0 is a no-op.
+ * Errors: MLFMA_EINVAL (null plan or buffer, nitems < 0), MLFMA_EDEVICE.
+ *
+ * mlfma_fft_info: items per workgroup and dynamic LDS bytes of the plan's
+ * kernel (host only).  mlfma_fft_destroy: NULL is a no-op.
+ */
+typedef struct mlfma_fft_s *mlfma_fft_t;
+int mlfma_fft_plan(int lband, int nphi_in, int nphi_out, int anterpolate, int device,
+                   mlfma_fft_t *out);
+int mlfma_fft_execute(mlfma_fft_t plan, const void *in, void *out, int64_t nitems,
+                      void *stream);
+int mlfma_fft_info(mlfma_fft_t plan, int *items_per_workgroup, int64_t *lds_bytes);
+void mlfma_fft_destroy(mlfma_fft_t plan);
+
 /* Host-side queries (no device call). */
 int mlfma_tree_info_get(mlfma_tree_t t, mlfma_tree_info *out);
 /* perm[s] = caller index of the point at Morton-sorted position s; host [n] */

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libmlfma.so")
 
 HOST_SOURCES = ["tree.cpp", "operators.cpp"]
 HIP_SOURCES = ["kernels.hip", "m2l.hip", "interp.hip", "fused.hip", "pair.hip", "solver.hip",
-               "capi.hip"]
+               "fft.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

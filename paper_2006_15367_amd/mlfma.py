@@ -95,6 +95,13 @@ EXPORTS = {
                            ctypes.c_int),
     "mlfma_ops_set_variant": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
                               ctypes.c_int),
+    "mlfma_fft_plan": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "mlfma_fft_execute": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                           ctypes.c_void_p], ctypes.c_int),
+    "mlfma_fft_info": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "mlfma_fft_destroy": ([ctypes.c_void_p], None),
     "mlfma_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "mlfma_last_error": ([], ctypes.c_char_p),
 }
@@ -383,6 +390,53 @@ class Operators:
     def close(self):
         if getattr(self, "_h", None):
             _load().mlfma_destroy_ops(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FFTResampler:
+    """FFT interpolation (or, with anterpolate=True, its weighted adjoint)
+    between uniform sphere grids of nphi_in and nphi_out phi samples
+    (see mlfma_fft_plan).  Call with a complex64 device tensor
+    [n, nphi_in // 2, nphi_in]; returns [n, nphi_out // 2, nphi_out]."""
+
+    def __init__(self, lband, nphi_in, nphi_out, anterpolate=False, device=0):
+        h = ctypes.c_void_p()
+        _check(_load().mlfma_fft_plan(int(lband), int(nphi_in), int(nphi_out),
+                                      1 if anterpolate else 0, int(device), ctypes.byref(h)),
+               "mlfma_fft_plan")
+        self._h = h
+        self.lband, self.nphi_in, self.nphi_out = int(lband), int(nphi_in), int(nphi_out)
+        self.anterpolate = bool(anterpolate)
+
+    def info(self):
+        ipw = ctypes.c_int()
+        lds = ctypes.c_int64()
+        _check(_load().mlfma_fft_info(self._h, ctypes.byref(ipw), ctypes.byref(lds)),
+               "mlfma_fft_info")
+        return {"items_per_workgroup": ipw.value, "lds_bytes": lds.value}
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        pi, po = self.nphi_in, self.nphi_out
+        if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous():
+            raise TypeError("input must be a contiguous complex64 device tensor")
+        if x.dim() != 3 or x.shape[1] != pi // 2 or x.shape[2] != pi:
+            raise ValueError("input must have shape [n, %d, %d]" % (pi // 2, pi))
+        if out is None:
+            out = torch.empty((x.shape[0], po // 2, po), dtype=torch.complex64, device=x.device)
+        _check(_load().mlfma_fft_execute(self._h, x.data_ptr(), out.data_ptr(), x.shape[0],
+                                         _stream_ptr(stream)), "mlfma_fft_execute")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().mlfma_fft_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -85,3 +85,22 @@ def test_phase_rooflines_sum_the_kernels_of_each_phase():
     assert abs(floor - expect) < 1e-12
     ph3, _ = bench.phase_rooflines(work, ms, True)
     assert ph3["m2m"]["peak"] == bench.PEAK_BF16_TFLOPS
+
+
+def test_fft_grid_sizes_are_7_smooth_and_minimal():
+    import bench
+    for L in range(0, 200):
+        P = bench.smooth_phi_count(L)
+        assert P % 2 == 0 and P >= 2 * L + 2
+        m = P
+        for r in (2, 3, 5, 7):
+            while m % r == 0:
+                m //= r
+        assert m == 1
+        for Q in range(2 * L + 2, P, 2):
+            m = Q
+            for r in (2, 3, 5, 7):
+                while m % r == 0:
+                    m //= r
+            assert m != 1, (L, Q)
+    assert [bench.smooth_phi_count(L) for L in (8, 13, 20, 33, 57)] == [18, 28, 42, 70, 120]

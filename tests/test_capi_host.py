@@ -191,3 +191,31 @@ def test_solve_gmres_argument_errors():
                     ctypes.byref(it), ctypes.byref(rr), None)
             assert st == G.EINVAL, (fn, sh, restart, maxit, tol)
             assert it.value == 0 and rr.value == 0.0
+
+
+def test_fft_plan_argument_errors():
+    """mlfma_fft_plan validates the sizes before it touches a device; the
+    execute/info calls reject a null plan."""
+    lib = G._load()
+    h = ctypes.c_void_p(123)
+    bad = [
+        (-1, 18, 28),    # negative band
+        (8, 17, 28),     # odd phi count
+        (8, 16, 28),     # below 2 lband + 2
+        (8, 18, 26),     # output below 2 lband + 2
+        (8, 18, 34),     # prime factor 17
+        (8, 22, 28),     # prime factor 11
+        (8, 18, 1026),   # above 1024
+        (60, 122, 126),  # 7-smooth? 122 = 2 x 61: no
+        (100, 210, 210),  # one item's LDS above 160 KiB
+    ]
+    for lb, pi, po in bad:
+        for ant in (0, 1):
+            h.value = 123
+            assert lib.mlfma_fft_plan(lb, pi, po, ant, 0, ctypes.byref(h)) == G.EINVAL, \
+                (lb, pi, po)
+            assert not h.value
+    assert lib.mlfma_fft_plan(8, 18, 28, 0, 0, None) == G.EINVAL
+    assert lib.mlfma_fft_execute(None, None, None, 1, None) == G.EINVAL
+    assert lib.mlfma_fft_info(None, None, None) == G.EINVAL
+    lib.mlfma_fft_destroy(None)
