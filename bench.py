@@ -284,12 +284,14 @@ def _dense_check(xyz, q, phi, ntgt=128, ncol=4):
     return float(np.linalg.norm(pp - ref) / np.linalg.norm(ref))
 
 
-def extra_workloads(headline_ms, steps=5, warmup=2):
+def extra_workloads(headline_ms, headline_operator_bytes=None, steps=5, warmup=2):
     """The other benchmark configurations, timed in the same run (inputs
     resident, default schedule): the elongated cloud with its tip cluster,
-    64 right-hand sides in FP32 and with BF16x3 interpolation, and the
-    volume cloud with 16 right-hand sides (matvec, and loss + backward of
-    ||phi - phi_target||^2 through the adjoint and field passes)."""
+    64 right-hand sides in FP32 and with BF16x3 interpolation, the volume
+    cloud with 16 right-hand sides (matvec, and loss + backward of
+    ||phi - phi_target||^2 through the adjoint and field passes), and the
+    benchmark sphere and the elongated cloud with sampled translation
+    operators (operator memory against the full tables)."""
     import gc
     import torch
     from paper_2006_15367_amd import mlfma as G
@@ -297,16 +299,20 @@ def extra_workloads(headline_ms, steps=5, warmup=2):
     from paper_2006_15367_amd.autograd import potential
     out = {}
     r64_fp32 = None
-    for key, name, bf in (("spheroid1m", "spheroid1m", False),
-                          ("sphere262k_r64", "sphere262k_r64", False),
-                          ("sphere262k_r64_bf16x3", "sphere262k_r64", True),
-                          ("cube1m_r16", "cube1m_r16", False)):
+    full_mem = {"sphere262k": headline_operator_bytes}
+    for key, name, bf, samp in (("spheroid1m", "spheroid1m", False, False),
+                                ("sphere262k_r64", "sphere262k_r64", False, False),
+                                ("sphere262k_r64_bf16x3", "sphere262k_r64", True, False),
+                                ("cube1m_r16", "cube1m_r16", False, False),
+                                ("sphere262k_sampled_operators", "sphere262k", False, True),
+                                ("spheroid1m_sampled_operators", "spheroid1m", False, True)):
         try:
             xyz, q = W.make(name)
             R = 1 if q.ndim == 1 else q.shape[1]
             t0 = time.perf_counter()
             tree = G.Tree(xyz, W.LEAF_SIZE)
-            ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=bf)
+            ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=bf,
+                              sampled=samp)
             torch.cuda.synchronize()
             setup = time.perf_counter() - t0
             qd = torch.from_numpy(np.ascontiguousarray(q.astype(np.complex64))).cuda()
@@ -319,6 +325,16 @@ def extra_workloads(headline_ms, steps=5, warmup=2):
                  "rel_l2_vs_dense_128_targets": _dense_check(xyz, q, phi.cpu().numpy())}
             if R > 1:
                 e["ms_per_rhs"] = round(ms / R, 4)
+            mem = ops.memory()
+            e["operator_bytes"] = mem["operator_bytes"]
+            if not samp and R == 1:
+                full_mem[name] = mem["operator_bytes"]
+            if samp:
+                e["m2l_variant_per_level"] = ops.variants("m2l")
+                if name == "sphere262k":
+                    e["slowdown_vs_full_tables_headline"] = round(ms / headline_ms, 3)
+                if full_mem.get(name):
+                    e["full_table_operator_bytes"] = full_mem[name]
             if name == "sphere262k_r64":
                 # same cloud as the headline: batched against single-RHS calls
                 e["speedup_per_rhs_vs_single_rhs_headline"] = round(headline_ms * R / ms, 3)
@@ -592,7 +608,7 @@ def main():
         except Exception as ex:  # keep the headline line whatever happens here
             out["fft_interpolation"] = {"error": "%s: %s" % (type(ex).__name__, ex)}
     if not args.no_extras and args.workload == "sphere262k" and not args.graph:
-        out["extra_workloads"] = extra_workloads(ms_per_step)
+        out["extra_workloads"] = extra_workloads(ms_per_step, ops.memory()["operator_bytes"])
     if not args.no_cpu_baseline:
         phi_np = phi.cpu().numpy().astype(np.complex128)
         out["cpu_baseline"] = cpu_baseline(xyz, q.astype(np.complex128), phi_np)

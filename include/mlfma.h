@@ -76,11 +76,20 @@ enum mlfma_flags {
                                 dtype, parts, stream) into a HIP graph once
                                 and replay it afterwards; calls on the null
                                 stream and profiled calls run eagerly       */
-    MLFMA_ONE_STREAM = 8     /* run every kernel on the caller's stream (by
+    MLFMA_ONE_STREAM = 8,    /* run every kernel on the caller's stream (by
                                 default the near field and the M2L of each
                                 level run on two library streams, forked
                                 from and joined back to the caller's stream
                                 with events, so they overlap the M2M chain) */
+    MLFMA_SAMPLED_OPERATORS = 16 /* keep the translation operators as sampled
+                                tables instead of their values at every grid
+                                direction (Sec. 3.2.3 "Translation Operators":
+                                sample and interpolate when memory is short):
+                                per distinct offset length, T at 8 L + 1
+                                angles to the offset; M2L interpolates its
+                                operators (10-point Lagrange, relative error
+                                below 3e-8) into LDS; M2L forms 3, 4 and 5
+                                only */
 };
 
 typedef struct mlfma_tree_info {
@@ -356,6 +365,13 @@ int mlfma_tree_far_list(mlfma_tree_t t, int level, int64_t *count,
 int mlfma_tree_near_list(mlfma_tree_t t, int64_t *start, int32_t *idx);
 /* info for levels 1..n_levels into out[0..n_levels-1] (max entries given) */
 int mlfma_ops_info(mlfma_ops_t ops, mlfma_level_info *out, int max_entries);
+/* Device bytes of the handle: *operator_bytes = the translation operator
+ * tables of every level (full tables and their antipodal and octant
+ * rearrangements, or the sampled tables), *total_bytes = the precompute's
+ * planned device bytes (an upper bound of what it allocated; the one
+ * mlfma_set_device_memory_limit is checked against).  Host only; either
+ * pointer may be NULL. */
+int mlfma_ops_memory(mlfma_ops_t ops, int64_t *operator_bytes, int64_t *total_bytes);
 
 /*
  * Diagnostics: copy the spectra the last call left in the workspace.

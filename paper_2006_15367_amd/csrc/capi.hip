@@ -35,6 +35,12 @@ struct DevLevel {
     int ntypes = 0;
     float4 *khat_w = nullptr;
     float2 *T = nullptr;
+    // sampled operators (MLFMA_SAMPLED_OPERATORS): tables [nrad][Msamp + 1]
+    // against the angle to the offset, unit offsets with their table row
+    float2 *Tsamp = nullptr;
+    float4 *xr = nullptr;
+    double *trig64 = nullptr;        // (cos, sin) of the theta nodes, then of phi
+    int Msamp = 0;
     int32_t *far_start = nullptr, *far_src = nullptr;
     int16_t *far_type = nullptr;
     int64_t n_far = 0;
@@ -123,6 +129,8 @@ struct mlfma_ops_s {
     float2 *gm_V = nullptr, *gm_w = nullptr;
     double2 *gm_part = nullptr, *gm_c = nullptr;
     int64_t planned_bytes = 0;       // device bytes of the precompute
+    int64_t operator_bytes = 0;      // of which translation operators
+    bool sampled = false;            // MLFMA_SAMPLED_OPERATORS
     hipEvent_t ev_fork = nullptr, ev_near = nullptr, ev_m2l = nullptr;
     std::vector<hipEvent_t> ev_S;  // per level: multipoles ready
     // captured graphs of previous calls (MLFMA_USE_GRAPH)
@@ -317,6 +325,19 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
 {
     DevLevel &D = o->lev[l];
     DevLevel &Pl = o->lev[l - 1];
+    if (o->sampled) {
+        // record kernel with the operator slice interpolated from the tables
+        if (variant < 3 || variant > 5) return hipErrorInvalidValue;
+        dev::SampledT st;
+        st.tab = D.Tsamp;
+        st.xr = D.xr;
+        st.trig = D.trig64;
+        st.nth = D.nth;
+        st.nph = D.nph;
+        st.M = D.Msamp;
+        return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
+                            D.rec_off, nullptr, D.S, R, D.Lloc, s, variant - 3, max_wg, st);
+    }
     switch (variant) {
     case 1:
         return dev::m2l_lds(D.nbox, D.K, D.ntypes, D.far_start, D.far_src, D.far_type, D.T, D.S,
@@ -434,6 +455,7 @@ int autotune(mlfma_ops_s *o)
         int bestv = 0;
         for (int v = 0; v < 9; ++v) {
             if (v >= 6 && R != 1) continue;  // variants 6, 7 and 8 serve one RHS
+            if (o->sampled && (v < 3 || v > 5)) continue;  // forms with sampled operators
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -805,7 +827,7 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     if (max_rhs < 1 || max_rhs > 1024)
         return fail(MLFMA_EINVAL, "precompute: max_rhs outside 1..1024");
     if (flags & ~(uint32_t)(MLFMA_BF16X3_INTERP | MLFMA_NO_AUTOTUNE | MLFMA_USE_GRAPH |
-                            MLFMA_ONE_STREAM))
+                            MLFMA_ONE_STREAM | MLFMA_SAMPLED_OPERATORS))
         return fail(MLFMA_EINVAL, "precompute: unknown flags");
     // the near-field kernels evaluate exp(ikr) on the hardware sine/cosine,
     // whose argument (in turns, k r / 2 pi) must stay within +-256; near
@@ -831,7 +853,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
     o->device = t->device;
     o->n = t->n;
     o->n_lev = t->n_lev;
-    int rc = build_level_tables(*t, k, digits, o->tab);
+    o->sampled = (flags & MLFMA_SAMPLED_OPERATORS) != 0;
+    int rc = build_level_tables(*t, k, digits, o->tab, o->sampled);
     if (rc) {
         free_ops(o);
         return rc;
@@ -856,17 +879,23 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             const LevelTables &T = o->tab[l];
             const HostLevel &H = t->lev[l];
             pl.add(T.K * 16);
-            pl.add((int64_t)T.ntypes * T.K * 8);
+            if (o->sampled)
+                pl.add((int64_t)T.Tsamp.size() * 4 + (int64_t)T.xr.size() * 4 +
+                       (int64_t)T.trig64.size() * 8);
+            else
+                pl.add((int64_t)T.ntypes * T.K * 8);
             pl.add((H.nbox + 1) * 4);
             pl.add((int64_t)H.far_src.size() * 6);
             pl.add(H.nbox * 5);
             pl.add((H.nbox + 1) * 4);
             pl.add(H.nbox * 4 + 343 * 2 + (H.nbox + 1) * 4 + 26 * H.nbox * 4);
             pl.add((int64_t)H.far_src.size() * 36 + (H.nbox + 1) * 4);  // M2L records (bound)
-            pl.add((int64_t)H.far_src.size() * 32);                     // antipodal record slots
-            pl.add(((int64_t)T.ntypes + 1) * (T.K / 2 + 64) * 8 + (T.K + 64) * 4);  // Tp, aperm
-            pl.add((int64_t)H.far_src.size() * 32);                     // octant record slots
-            pl.add(57 * (8 * T.K + 64) * 8 + (8 * T.K + 64) * 4);       // To, operm (bound)
+            if (!o->sampled) {
+                pl.add((int64_t)H.far_src.size() * 32);                 // antipodal record slots
+                pl.add(((int64_t)T.ntypes + 1) * (T.K / 2 + 64) * 8 + (T.K + 64) * 4);  // Tp
+                pl.add((int64_t)H.far_src.size() * 32);                 // octant record slots
+                pl.add(57 * (8 * T.K + 64) * 8 + (8 * T.K + 64) * 4);   // To, operm (bound)
+            }
             pl.add(H.nbox * R * T.K * 8 * 2);
             if (l < nl) {
                 const LevelTables &C = o->tab[l + 1];
@@ -958,7 +987,23 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             D.ntypes = T.ntypes;
             D.n_far = (int64_t)H.far_src.size();
             if ((r = upload(o, &D.khat_w, (const float4 *)T.khat_w.data(), T.K))) return r;
-            if ((r = upload(o, &D.T, (const float2 *)T.T.data(), (int64_t)T.ntypes * T.K))) return r;
+            if (o->sampled) {
+                if ((r = upload(o, &D.Tsamp, (const float2 *)T.Tsamp.data(),
+                                (int64_t)T.Tsamp.size() / 2)))
+                    return r;
+                if ((r = upload(o, &D.xr, (const float4 *)T.xr.data(), (int64_t)T.ntypes)))
+                    return r;
+                if ((r = upload(o, &D.trig64, T.trig64.data(), (int64_t)T.trig64.size())))
+                    return r;
+                D.Msamp = T.Msamp;
+                D.m2l_variant = 5;
+                o->operator_bytes += (int64_t)(T.Tsamp.size() + T.xr.size()) * 4 +
+                                     (int64_t)T.trig64.size() * 8;
+            } else {
+                if ((r = upload(o, &D.T, (const float2 *)T.T.data(), (int64_t)T.ntypes * T.K)))
+                    return r;
+                o->operator_bytes += (int64_t)T.ntypes * T.K * 8;
+            }
             if ((r = upload(o, &D.far_start, H.far_start.data(), H.nbox + 1))) return r;
             if ((r = upload(o, &D.far_src, H.far_src.data(), D.n_far))) return r;
             if ((r = upload(o, &D.far_type, T.far_type.data(), D.n_far))) return r;
@@ -1023,137 +1068,141 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 if ((r = upload(o, &D.rec_start, rs.data(), (int64_t)rs.size()))) return r;
                 if ((r = upload(o, &D.rec_src, rsrc.data(), (int64_t)rsrc.size()))) return r;
                 if ((r = upload(o, &D.rec_off, roff.data(), (int64_t)roff.size()))) return r;
-                // antipodal slices: the opposite of sample (i, j) is
-                // (nth - 1 - i, j + nph / 2); T_{-d}(k) = T_d(-k)
-                const int64_t K = T.K;
-                auto anti = [&](int64_t q) -> int64_t {
-                    const int64_t i = q / T.nph, j = q % T.nph;
-                    return (T.nth - 1 - i) * T.nph + (j + T.nph / 2) % T.nph;
-                };
-                std::vector<int64_t> canon;
-                for (int64_t q = 0; q < K; ++q)
-                    if (q < anti(q)) canon.push_back(q);
-                const int64_t npair = (int64_t)canon.size();
-                const int64_t nsl = (npair + 31) / 32;
-                D.Kp = nsl * 64;
-                std::vector<int32_t> ap((size_t)D.Kp, -1);
-                for (int64_t sl = 0; sl < nsl; ++sl)
-                    for (int ln = 0; ln < 32; ++ln) {
-                        const int64_t pr = sl * 32 + ln;
-                        if (pr >= npair) break;
-                        ap[(size_t)(sl * 64 + ln)] = (int32_t)canon[(size_t)pr];
-                        ap[(size_t)(sl * 64 + 63 - ln)] = (int32_t)anti(canon[(size_t)pr]);
+                // the antipodal and octant forms copy from the full table
+                if (!o->sampled) {
+                    // antipodal slices: the opposite of sample (i, j) is
+                    // (nth - 1 - i, j + nph / 2); T_{-d}(k) = T_d(-k)
+                    const int64_t K = T.K;
+                    auto anti = [&](int64_t q) -> int64_t {
+                        const int64_t i = q / T.nph, j = q % T.nph;
+                        return (T.nth - 1 - i) * T.nph + (j + T.nph / 2) % T.nph;
+                    };
+                    std::vector<int64_t> canon;
+                    for (int64_t q = 0; q < K; ++q)
+                        if (q < anti(q)) canon.push_back(q);
+                    const int64_t npair = (int64_t)canon.size();
+                    const int64_t nsl = (npair + 31) / 32;
+                    D.Kp = nsl * 64;
+                    std::vector<int32_t> ap((size_t)D.Kp, -1);
+                    for (int64_t sl = 0; sl < nsl; ++sl)
+                        for (int ln = 0; ln < 32; ++ln) {
+                            const int64_t pr = sl * 32 + ln;
+                            if (pr >= npair) break;
+                            ap[(size_t)(sl * 64 + ln)] = (int32_t)canon[(size_t)pr];
+                            ap[(size_t)(sl * 64 + 63 - ln)] = (int32_t)anti(canon[(size_t)pr]);
+                        }
+                    // offset pairs: code(-d) = 342 - code(d); the smaller code
+                    // of a used pair names it
+                    std::vector<int> tp_of(343, -1), type_code(T.ntypes, -1);
+                    int ntp = 0;
+                    for (int c = 0; c < 343; ++c) {
+                        if (T.code_to_type[c] < 0) continue;
+                        type_code[T.code_to_type[c]] = c;
+                        const int c0 = std::min(c, 342 - c);
+                        if (tp_of[c0] < 0) tp_of[c0] = ntp++;
                     }
-                // offset pairs: code(-d) = 342 - code(d); the smaller code
-                // of a used pair names it
-                std::vector<int> tp_of(343, -1), type_code(T.ntypes, -1);
-                int ntp = 0;
-                for (int c = 0; c < 343; ++c) {
-                    if (T.code_to_type[c] < 0) continue;
-                    type_code[T.code_to_type[c]] = c;
-                    const int c0 = std::min(c, 342 - c);
-                    if (tp_of[c0] < 0) tp_of[c0] = ntp++;
-                }
-                D.ntp = ntp;
-                std::vector<float2> tpv((size_t)ntp * D.Kp, make_float2(0.f, 0.f));
-                const float2 *Th = (const float2 *)T.T.data();
-                for (int c0 = 0; c0 < 343; ++c0) {
-                    if (tp_of[c0] < 0) continue;
-                    // the row of offset c0, or the mirrored row of -c0
-                    const bool direct = T.code_to_type[c0] >= 0;
-                    const int t = direct ? T.code_to_type[c0] : T.code_to_type[342 - c0];
-                    for (int64_t e = 0; e < D.Kp; ++e) {
-                        const int32_t q = ap[(size_t)e];
-                        if (q < 0) continue;
-                        tpv[(size_t)tp_of[c0] * D.Kp + e] = Th[(size_t)t * K + (direct ? q : anti(q))];
+                    D.ntp = ntp;
+                    std::vector<float2> tpv((size_t)ntp * D.Kp, make_float2(0.f, 0.f));
+                    const float2 *Th = (const float2 *)T.T.data();
+                    for (int c0 = 0; c0 < 343; ++c0) {
+                        if (tp_of[c0] < 0) continue;
+                        // the row of offset c0, or the mirrored row of -c0
+                        const bool direct = T.code_to_type[c0] >= 0;
+                        const int t = direct ? T.code_to_type[c0] : T.code_to_type[342 - c0];
+                        for (int64_t e = 0; e < D.Kp; ++e) {
+                            const int32_t q = ap[(size_t)e];
+                            if (q < 0) continue;
+                            tpv[(size_t)tp_of[c0] * D.Kp + e] = Th[(size_t)t * K + (direct ? q : anti(q))];
+                        }
                     }
-                }
-                std::vector<int32_t> ranti(roff.size());
-                for (size_t e = 0; e < roff.size(); ++e) {
-                    if (roff[e] == zero_row) {
-                        ranti[e] = ntp * 512;
-                        continue;
+                    std::vector<int32_t> ranti(roff.size());
+                    for (size_t e = 0; e < roff.size(); ++e) {
+                        if (roff[e] == zero_row) {
+                            ranti[e] = ntp * 512;
+                            continue;
+                        }
+                        const int c = type_code[roff[e] / (64 * (int32_t)sizeof(float2))];
+                        const int c0 = std::min(c, 342 - c);
+                        ranti[e] = tp_of[c0] * 512 | (c != c0 ? 504 : 0);
                     }
-                    const int c = type_code[roff[e] / (64 * (int32_t)sizeof(float2))];
-                    const int c0 = std::min(c, 342 - c);
-                    ranti[e] = tp_of[c0] * 512 | (c != c0 ? 504 : 0);
-                }
-                if ((r = upload(o, &D.Tp, tpv.data(), (int64_t)tpv.size()))) return r;
-                if ((r = upload(o, &D.aperm, ap.data(), D.Kp))) return r;
-                if ((r = upload(o, &D.rec_off_anti, ranti.data(), (int64_t)ranti.size()))) return r;
+                    if ((r = upload(o, &D.Tp, tpv.data(), (int64_t)tpv.size()))) return r;
+                    if ((r = upload(o, &D.aperm, ap.data(), D.Kp))) return r;
+                    if ((r = upload(o, &D.rec_off_anti, ranti.data(), (int64_t)ranti.size()))) return r;
 
-                // octant slices: reflection g (bit 2: x, phi -> pi - phi;
-                // bit 1: y, phi -> -phi; bit 0: z, theta -> pi - theta) of
-                // sample q; the reflected offset R_g d has T_{R_g d}(q) =
-                // T_d(refl(g, q))
-                auto refl = [&](int g, int64_t q) -> int64_t {
-                    int64_t i = q / T.nph, j = q % T.nph;
-                    if (g & 1) i = T.nth - 1 - i;
-                    if (g & 2) j = (T.nph - j) % T.nph;
-                    if (g & 4) j = (T.nph / 2 - j + T.nph) % T.nph;
-                    return i * T.nph + j;
-                };
-                std::vector<char> seen((size_t)K, 0);
-                std::vector<int64_t> orbit0;
-                for (int64_t q = 0; q < K; ++q) {
-                    if (seen[(size_t)q]) continue;
-                    orbit0.push_back(q);
-                    for (int g = 0; g < 8; ++g) seen[(size_t)refl(g, q)] = 1;
-                }
-                const int64_t nso = ((int64_t)orbit0.size() + 7) / 8;
-                D.Ko = nso * 64;
-                std::vector<int32_t> opm((size_t)D.Ko, -1);
-                for (size_t ob = 0; ob < orbit0.size(); ++ob)
-                    for (int g = 0; g < 8; ++g) {
-                        const int64_t q = refl(g, orbit0[ob]);
-                        bool first = true;
-                        for (int h = 0; h < g; ++h)
-                            if (refl(h, orbit0[ob]) == q) first = false;
-                        opm[ob * 8 + g] = first ? (int32_t)q : (int32_t)(-q - 2);
+                    // octant slices: reflection g (bit 2: x, phi -> pi - phi;
+                    // bit 1: y, phi -> -phi; bit 0: z, theta -> pi - theta) of
+                    // sample q; the reflected offset R_g d has T_{R_g d}(q) =
+                    // T_d(refl(g, q))
+                    auto refl = [&](int g, int64_t q) -> int64_t {
+                        int64_t i = q / T.nph, j = q % T.nph;
+                        if (g & 1) i = T.nth - 1 - i;
+                        if (g & 2) j = (T.nph - j) % T.nph;
+                        if (g & 4) j = (T.nph / 2 - j + T.nph) % T.nph;
+                        return i * T.nph + j;
+                    };
+                    std::vector<char> seen((size_t)K, 0);
+                    std::vector<int64_t> orbit0;
+                    for (int64_t q = 0; q < K; ++q) {
+                        if (seen[(size_t)q]) continue;
+                        orbit0.push_back(q);
+                        for (int g = 0; g < 8; ++g) seen[(size_t)refl(g, q)] = 1;
                     }
-                // rows: the offsets (|dx|, |dy|, |dz|) of the used offsets
-                std::vector<int> row_of(64, -1), src_code(64, -1);
-                int nto = 0;
-                for (int c = 0; c < 343; ++c) {
-                    if (T.code_to_type[c] < 0) continue;
-                    const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
-                    const int a = std::abs(dx) * 16 + std::abs(dy) * 4 + std::abs(dz);
-                    if (row_of[a] < 0) {
-                        row_of[a] = nto++;
-                        src_code[a] = c;
+                    const int64_t nso = ((int64_t)orbit0.size() + 7) / 8;
+                    D.Ko = nso * 64;
+                    std::vector<int32_t> opm((size_t)D.Ko, -1);
+                    for (size_t ob = 0; ob < orbit0.size(); ++ob)
+                        for (int g = 0; g < 8; ++g) {
+                            const int64_t q = refl(g, orbit0[ob]);
+                            bool first = true;
+                            for (int h = 0; h < g; ++h)
+                                if (refl(h, orbit0[ob]) == q) first = false;
+                            opm[ob * 8 + g] = first ? (int32_t)q : (int32_t)(-q - 2);
+                        }
+                    // rows: the offsets (|dx|, |dy|, |dz|) of the used offsets
+                    std::vector<int> row_of(64, -1), src_code(64, -1);
+                    int nto = 0;
+                    for (int c = 0; c < 343; ++c) {
+                        if (T.code_to_type[c] < 0) continue;
+                        const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+                        const int a = std::abs(dx) * 16 + std::abs(dy) * 4 + std::abs(dz);
+                        if (row_of[a] < 0) {
+                            row_of[a] = nto++;
+                            src_code[a] = c;
+                        }
                     }
-                }
-                D.nto = nto;
-                std::vector<float2> tov((size_t)nto * D.Ko, make_float2(0.f, 0.f));
-                for (int a = 0; a < 64; ++a) {
-                    if (row_of[a] < 0) continue;
-                    const int c = src_code[a];
-                    const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
-                    const int g = (dx < 0 ? 4 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 1 : 0);
-                    const int t = T.code_to_type[c];
-                    // T_{|d|}(q) = T_{R_g |d|}(refl(g, q)), R_g |d| = d
-                    for (int64_t e = 0; e < D.Ko; ++e) {
-                        const int32_t cd = opm[(size_t)e];
-                        if (cd == -1) continue;
-                        const int64_t q = cd >= 0 ? cd : -(int64_t)cd - 2;
-                        tov[(size_t)row_of[a] * D.Ko + e] = Th[(size_t)t * K + refl(g, q)];
+                    D.nto = nto;
+                    std::vector<float2> tov((size_t)nto * D.Ko, make_float2(0.f, 0.f));
+                    for (int a = 0; a < 64; ++a) {
+                        if (row_of[a] < 0) continue;
+                        const int c = src_code[a];
+                        const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+                        const int g = (dx < 0 ? 4 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 1 : 0);
+                        const int t = T.code_to_type[c];
+                        // T_{|d|}(q) = T_{R_g |d|}(refl(g, q)), R_g |d| = d
+                        for (int64_t e = 0; e < D.Ko; ++e) {
+                            const int32_t cd = opm[(size_t)e];
+                            if (cd == -1) continue;
+                            const int64_t q = cd >= 0 ? cd : -(int64_t)cd - 2;
+                            tov[(size_t)row_of[a] * D.Ko + e] = Th[(size_t)t * K + refl(g, q)];
+                        }
                     }
-                }
-                std::vector<int32_t> roct(roff.size());
-                for (size_t e = 0; e < roff.size(); ++e) {
-                    if (roff[e] == zero_row) {
-                        roct[e] = nto * 512;
-                        continue;
+                    std::vector<int32_t> roct(roff.size());
+                    for (size_t e = 0; e < roff.size(); ++e) {
+                        if (roff[e] == zero_row) {
+                            roct[e] = nto * 512;
+                            continue;
+                        }
+                        const int c = type_code[roff[e] / (64 * (int32_t)sizeof(float2))];
+                        const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
+                        const int a = std::abs(dx) * 16 + std::abs(dy) * 4 + std::abs(dz);
+                        const int g = (dx < 0 ? 4 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 1 : 0);
+                        roct[e] = row_of[a] * 512 | (g * 8);
                     }
-                    const int c = type_code[roff[e] / (64 * (int32_t)sizeof(float2))];
-                    const int dx = c / 49 - 3, dy = (c / 7) % 7 - 3, dz = c % 7 - 3;
-                    const int a = std::abs(dx) * 16 + std::abs(dy) * 4 + std::abs(dz);
-                    const int g = (dx < 0 ? 4 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 1 : 0);
-                    roct[e] = row_of[a] * 512 | (g * 8);
+                    if ((r = upload(o, &D.To, tov.data(), (int64_t)tov.size()))) return r;
+                    if ((r = upload(o, &D.operm, opm.data(), D.Ko))) return r;
+                    if ((r = upload(o, &D.rec_off_oct, roct.data(), (int64_t)roct.size()))) return r;
+                    o->operator_bytes += ((int64_t)D.ntp * D.Kp + (int64_t)D.nto * D.Ko) * 8;
                 }
-                if ((r = upload(o, &D.To, tov.data(), (int64_t)tov.size()))) return r;
-                if ((r = upload(o, &D.operm, opm.data(), D.Ko))) return r;
-                if ((r = upload(o, &D.rec_off_oct, roct.data(), (int64_t)roct.size()))) return r;
             }
             {
                 std::vector<int32_t> bs(H.nbox);
@@ -1755,6 +1804,9 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
         if (variant < 0 || variant > 8) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (o->sampled && (variant < 3 || variant > 5))
+            return fail(MLFMA_EINVAL, "ops_set_variant: M2L form %d needs full operator tables",
+                        variant);
         o->lev[level].m2l_variant = variant;
     } else if (kernel == MLFMA_K_INTERP || kernel == MLFMA_K_ANTERP) {
         if (level < 3 || level >= o->n_lev)
@@ -1838,6 +1890,14 @@ int mlfma_profile_end(mlfma_ops_t o, double *ms, int64_t *launches)
     }
     prof_release(o);
     return rc;
+}
+
+int mlfma_ops_memory(mlfma_ops_t o, int64_t *operator_bytes, int64_t *total_bytes)
+{
+    if (!o) return fail(MLFMA_EINVAL, "ops_memory: ops is NULL");
+    if (operator_bytes) *operator_bytes = o->operator_bytes;
+    if (total_bytes) *total_bytes = o->planned_bytes;
+    return MLFMA_OK;
 }
 
 const char *mlfma_status_string(int status)

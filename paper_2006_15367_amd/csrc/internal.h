@@ -65,6 +65,14 @@ struct LevelTables {
     std::vector<int16_t> code_to_type; // [343] -> compact operator index or -1
     int ntypes = 0;
     std::vector<float> T;            // [ntypes][K][2] translation operators
+    // sampled operators (instead of T): per distinct offset length a table
+    // of T at gamma_m = m pi / Msamp, m = 0..Msamp, against the angle gamma
+    // between the direction and the offset; per operator its integer
+    // offset and table row
+    int Msamp = 0, nrad = 0;
+    std::vector<float> Tsamp;        // [nrad][Msamp + 1][2]
+    std::vector<float> xr;           // [ntypes][4]: integer offset (dx, dy, dz), row
+    std::vector<double> trig64;      // (cos, sin) of each theta node, then of each phi
     std::vector<int16_t> far_type;   // far list in compact operator indices
     // level pair (this level = parent p, level+1 = child c); empty at the leaf
     int Lc = 0, Mc = 0;              // child order, 2 Lc + 1 real-DFT columns
@@ -80,7 +88,12 @@ struct LevelTables {
 };
 
 int truncation_order(double k, double a, int digits);
+// oversampling of the sampled operators' tables and their stencil width
+constexpr int kSampledOversample = 8;
+constexpr int kSampledPoints = 10;
+// sampled = true: the translation operators as sampled tables (Tsamp, xr)
+// instead of their values on the grid (T)
 int build_level_tables(const Tree &t, double k, int digits,
-                       std::vector<LevelTables> &out);
+                       std::vector<LevelTables> &out, bool sampled = false);
 
 }  // namespace mlfma

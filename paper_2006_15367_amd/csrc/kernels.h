@@ -138,10 +138,26 @@ hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_st
                     const float2 *Tp, const int32_t *aperm, int64_t Kp, const float2 *S,
                     float2 *Lout, hipStream_t s, int max_wg = 0, int waves = 16);
 
+// Sampled translation operators (Sec. 3.2.3 "Translation Operators"): per
+// distinct offset length a table of T at gamma_m = m pi / M (m = 0..M)
+// against the angle gamma between the direction and the offset, and per
+// operator its integer offset with the table row in w; the M2L record
+// kernel interpolates its LDS slice of operators from them (10-point
+// Lagrange, mirrored at 0 and pi) instead of copying it from a full table.
+struct SampledT {
+    const float2 *tab = nullptr;    // [nrad][M + 1]
+    const float4 *xr = nullptr;     // [ntypes]: integer offset (dx, dy, dz), table row
+    // grid directions in FP64: (cos, sin) of theta_i at [2 i], of phi_j at
+    // [2 nth + 2 j]; sample k = i nph + j
+    const double *trig = nullptr;
+    int nth = 0, nph = 0;
+    int M = 0;
+};
+
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
-                   int schedule, int max_wg = 0);
+                   int schedule, int max_wg = 0, SampledT sampled = SampledT());
 
 // M2L per observer with the operator slice in LDS
 hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start,

@@ -68,6 +68,66 @@ __device__ __forceinline__ void stage_t_slice(float2 *Ts, const float2 *__restri
     }
 }
 
+// The same slice interpolated from sampled operators: for operator t and
+// sample k, gamma = the angle between khat_k and the integer offset d_t
+// (atan2 of the norm of the cross product and the dot product, in FP64:
+// the interpolant moves by up to 0.4 max|T| per table spacing, and an FP32
+// angle would be off by about 1e-5 of a spacing at M = 456), x = gamma M /
+// pi, and T = sum_j w_j tab[row][m0 + j], m0 = floor(x) - 4, j = 0..9,
+// with the Lagrange weights w_j = prod_{i != j} (f + 4 - i) / (j - i) of
+// the fraction f = x - floor(x) in FP32; indices below 0 or above M mirror
+// (T is even about 0 and about pi).
+template <int KC>
+__device__ void stage_t_interp(float2 *Ts, SampledT st, int ntypes, int64_t K, int64_t k0)
+{
+    constexpr int P = 10;
+    // 1 / prod_{i != j} (j - i)
+    constexpr float cw[P] = {1.f / -362880.f, 1.f / 40320.f, 1.f / -10080.f, 1.f / 4320.f,
+                             1.f / -2880.f,   1.f / 2880.f,  1.f / -4320.f,  1.f / 10080.f,
+                             1.f / -40320.f,  1.f / 362880.f};
+    const int total = ntypes * KC;
+    const int M = st.M;
+    const double scale = (double)M * 0.318309886183790671537767526745;  // M / pi
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int t = idx / KC, kk = idx % KC;
+        float2 v = make_float2(0.f, 0.f);
+        if (k0 + kk < K) {
+            const int ki = (int)(k0 + kk);
+            const int ti = ki / st.nph, pj = ki - ti * st.nph;
+            const double ct = st.trig[2 * ti], sn = st.trig[2 * ti + 1];
+            const double cp = st.trig[2 * st.nth + 2 * pj], sp = st.trig[2 * st.nth + 2 * pj + 1];
+            const double kx = sn * cp, ky = sn * sp, kz = ct;
+            const float4 xr = st.xr[t];
+            const double dx = xr.x, dy = xr.y, dz = xr.z;
+            const double c = kx * dx + ky * dy + kz * dz;
+            const double cx = ky * dz - kz * dy, cy = kz * dx - kx * dz, cz = kx * dy - ky * dx;
+            const double x = atan2(sqrt(cx * cx + cy * cy + cz * cz), c) * scale;
+            const double fl = floor(x);
+            const float f = (float)(x - fl);
+            const int m0 = (int)fl - 4;
+            float pre[P], suf[P];
+            pre[0] = 1.f;
+#pragma unroll
+            for (int j = 1; j < P; ++j) pre[j] = pre[j - 1] * (f + (float)(5 - j));
+            suf[P - 1] = 1.f;
+#pragma unroll
+            for (int j = P - 2; j >= 0; --j) suf[j] = suf[j + 1] * (f + (float)(3 - j));
+            const float2 *row = st.tab + (int64_t)(int)xr.w * (M + 1);
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                int m = m0 + j;
+                m = m < 0 ? -m : m;
+                m = m > M ? 2 * M - m : m;
+                const float w = pre[j] * suf[j] * cw[j];
+                const float2 tv = row[m];
+                v.x += w * tv.x;
+                v.y += w * tv.y;
+            }
+        }
+        Ts[idx] = v;
+    }
+}
+
 // One wave per (observer box, chunk of 64 samples): the far list of the box
 // is wave-uniform (scalar loads), lanes run over samples, each translation
 // operator and source spectrum is read once per wave and reused for RC
@@ -473,13 +533,13 @@ __device__ __forceinline__ void m2l_rec_parent(const char *Tsb, int lane8, int e
     }
 }
 
-template <int RC, int NW>
+template <int RC, int NW, bool SAMPLED>
 __global__ void __launch_bounds__(64 * NW)
 k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ child_start,
           const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
           const int32_t *__restrict__ rec_off, const float2 *__restrict__ T,
           const float2 *__restrict__ S, int R, int nkc, int nrange, int nwg, int balanced,
-          float2 *__restrict__ Lout)
+          float2 *__restrict__ Lout, SampledT sampled)
 {
     // Two schedules (about one workgroup per CU either way, so the LDS
     // staging of the operators is amortised over many parents):
@@ -507,7 +567,10 @@ k_m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ ch
     const int64_t slice = nwg ? blockIdx.x / nwg : 0;
     const int kc = nwg ? (int)(slice % nkc) : (int)(w % nkc);
     const int64_t k0 = (int64_t)kc * 64;
-    stage_t_slice<64>(Ts, T, ntypes, K, k0);
+    if constexpr (SAMPLED)
+        stage_t_interp<64>(Ts, sampled, ntypes, K, k0);
+    else
+        stage_t_slice<64>(Ts, T, ntypes, K, k0);
     for (int idx = threadIdx.x; idx < 64; idx += blockDim.x)
         Ts[ntypes * 64 + idx] = make_float2(0.f, 0.f);
     if (threadIdx.x == 0) next_parent = 0;
@@ -870,10 +933,12 @@ hipError_t m2l_anti(int64_t nparent, int64_t K, int ntp, const int32_t *child_st
 hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
-                   int schedule, int max_wg)
+                   int schedule, int max_wg, SampledT sampled)
 {
     const bool sweep = schedule == 1;
     if (nparent == 0 || K == 0) return hipSuccess;
+    // the 32-sample form copies from the full table only
+    if (sampled.tab && schedule == 3) return hipErrorInvalidValue;
     if (schedule == 3 && R == 1) {
         // one RHS, 32-sample slice, two workgroups per CU
         const size_t lds2 = (size_t)(ntypes + 1) * 32 * sizeof(float2);
@@ -917,12 +982,17 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
                                           ((nparent + nrange - 1) / nrange));
         grid = dim3((unsigned)(nkc * nrange), 1, (unsigned)nz);
     }
-#define M2L_REC(RCV, NWV)                                                                      \
-    M2L_LAUNCH((k_m2l_rec<RCV, NWV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
+#define M2L_REC(RCV, NWV, SV)                                                                  \
+    M2L_LAUNCH((k_m2l_rec<RCV, NWV, SV>), grid, dim3(64 * NWV), lds, s, nparent, K, ntypes, \
                        child_start, rec_start, rec_src, rec_off, T, S, R, nkc, nrange, nwg,   \
-                       schedule == 2 ? 1 : 0, Lout)
-    if (RC == 1) M2L_REC(1, 16);
-    else M2L_REC(4, 16);
+                       schedule == 2 ? 1 : 0, Lout, sampled)
+    if (sampled.tab) {
+        if (RC == 1) M2L_REC(1, 16, true);
+        else M2L_REC(4, 16, true);
+    } else {
+        if (RC == 1) M2L_REC(1, 16, false);
+        else M2L_REC(4, 16, false);
+    }
 #undef M2L_REC
     return hipGetLastError();
 }

@@ -165,7 +165,8 @@ static void legendre_maps(int Lband, const std::vector<double> &xf, const std::v
     });
 }
 
-int build_level_tables(const Tree &t, double k, int digits, std::vector<LevelTables> &out)
+int build_level_tables(const Tree &t, double k, int digits, std::vector<LevelTables> &out,
+                       bool sampled)
 {
     out.clear();
     out.resize(t.n_lev + 1);
@@ -205,8 +206,74 @@ int build_level_tables(const Tree &t, double k, int digits, std::vector<LevelTab
             T.far_type.resize(HL.far_code.size());
             for (size_t e = 0; e < HL.far_code.size(); ++e)
                 T.far_type[e] = T.code_to_type[HL.far_code[e]];
-            T.T.assign((size_t)T.ntypes * T.K * 2, 0.f);
             const double a = HL.a;
+            if (sampled) {
+                // Sec. 3.2.3 "Translation Operators": sampled operators.  T
+                // depends on the direction only through the angle gamma to
+                // the offset and is a cosine polynomial of degree L in it;
+                // tabulate it per distinct offset length at M + 1 angles,
+                // M = 8 L, for interpolation at the grid directions.
+                std::vector<int> rad_of_n2(28, -1), n2_of_rad;
+                for (int code : codes) {
+                    const int dx = code / 49 - 3, dy = (code / 7) % 7 - 3, dz = code % 7 - 3;
+                    const int n2 = dx * dx + dy * dy + dz * dz;
+                    if (rad_of_n2[n2] < 0) {
+                        rad_of_n2[n2] = (int)n2_of_rad.size();
+                        n2_of_rad.push_back(n2);
+                    }
+                }
+                T.nrad = (int)n2_of_rad.size();
+                T.Msamp = kSampledOversample * T.L;
+                const int Ms = T.Msamp;
+                T.Tsamp.assign((size_t)T.nrad * (Ms + 1) * 2, 0.f);
+                run_parallel(T.nrad, [&](int ri) {
+                    const double r = a * std::sqrt((double)n2_of_rad[ri]);
+                    std::vector<cplx> h;
+                    hankel1(T.L, k * r, h);
+                    std::vector<cplx> coef(T.L + 1);
+                    cplx il(1.0, 0.0);
+                    for (int ll = 0; ll <= T.L; ++ll) {
+                        coef[ll] = il * (2.0 * ll + 1.0) * h[ll];
+                        il *= cplx(0.0, 1.0);
+                    }
+                    for (int m = 0; m <= Ms; ++m) {
+                        const double u = std::cos(M_PI * m / Ms);
+                        double p0 = 1.0, p1 = u;
+                        cplx sum = coef[0];
+                        if (T.L >= 1) sum += coef[1] * u;
+                        for (int ll = 1; ll < T.L; ++ll) {
+                            const double p2 = ((2.0 * ll + 1.0) * u * p1 - ll * p0) / (ll + 1.0);
+                            p0 = p1;
+                            p1 = p2;
+                            sum += coef[ll + 1] * p2;
+                        }
+                        float *o = &T.Tsamp[2 * ((size_t)ri * (Ms + 1) + m)];
+                        o[0] = (float)sum.real();
+                        o[1] = (float)sum.imag();
+                    }
+                });
+                T.xr.assign((size_t)T.ntypes * 4, 0.f);
+                for (int ti = 0; ti < T.ntypes; ++ti) {
+                    const int code = codes[ti];
+                    const int dx = code / 49 - 3, dy = (code / 7) % 7 - 3, dz = code % 7 - 3;
+                    T.xr[4 * ti + 0] = (float)dx;
+                    T.xr[4 * ti + 1] = (float)dy;
+                    T.xr[4 * ti + 2] = (float)dz;
+                    T.xr[4 * ti + 3] = (float)rad_of_n2[dx * dx + dy * dy + dz * dz];
+                }
+                T.trig64.resize((size_t)2 * (T.nth + T.nph));
+                for (int i = 0; i < T.nth; ++i) {
+                    T.trig64[2 * i] = T.x[i];
+                    T.trig64[2 * i + 1] = std::sqrt((1.0 - T.x[i]) * (1.0 + T.x[i]));
+                }
+                for (int j = 0; j < T.nph; ++j) {
+                    const double ph = 2.0 * M_PI * j / T.nph;
+                    T.trig64[2 * (T.nth + j)] = std::cos(ph);
+                    T.trig64[2 * (T.nth + j) + 1] = std::sin(ph);
+                }
+                continue;
+            }
+            T.T.assign((size_t)T.ntypes * T.K * 2, 0.f);
             run_parallel(T.ntypes, [&](int ti) {
                 const int code = codes[ti];
                 const double dx = code / 49 - 3, dy = (code / 7) % 7 - 3, dz = code % 7 - 3;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libmlfma.so")
 OK, EINVAL, EDEPTH, ENOMEM, EDEVICE, ERANGE = range(6)
 C64, C128 = 0, 1
 NEAR, FAR, CONJ = 1, 2, 4
-FP32, BF16X3_INTERP, NO_AUTOTUNE, USE_GRAPH, ONE_STREAM = 0, 1, 2, 4, 8
+FP32, BF16X3_INTERP, NO_AUTOTUNE, USE_GRAPH, ONE_STREAM, SAMPLED_OPERATORS = 0, 1, 2, 4, 8, 16
 PROFILE_SERIAL = 0x80000000
 KERNELS = ["gather", "p2p", "c2m", "interp_s1", "interp_s2", "interp_s3", "m2l",
            "anterp_s1", "anterp_s2", "anterp_s3", "l2o", "interp", "anterp"]
@@ -95,6 +95,8 @@ EXPORTS = {
                            ctypes.c_int),
     "mlfma_ops_set_variant": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
                               ctypes.c_int),
+    "mlfma_ops_memory": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "mlfma_fft_plan": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "mlfma_fft_execute": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -245,11 +247,12 @@ class Operators:
     mlfma_precompute_operators)."""
 
     def __init__(self, tree, k, digits=3, max_rhs=1, bf16x3=False, autotune=True, graph=False,
-                 one_stream=False):
+                 one_stream=False, sampled=False):
         lib = _load()
         h = ctypes.c_void_p()
         flags = ((BF16X3_INTERP if bf16x3 else FP32) | (0 if autotune else NO_AUTOTUNE)
-                 | (USE_GRAPH if graph else 0) | (ONE_STREAM if one_stream else 0))
+                 | (USE_GRAPH if graph else 0) | (ONE_STREAM if one_stream else 0)
+                 | (SAMPLED_OPERATORS if sampled else 0))
         _check(lib.mlfma_precompute_operators(tree.handle, float(k), int(digits),
                                               int(max_rhs), flags, ctypes.byref(h)),
                "mlfma_precompute_operators")
@@ -259,6 +262,14 @@ class Operators:
         self.k = float(k)
         self.max_rhs = int(max_rhs)
         self.device = tree.device
+
+    def memory(self):
+        """{"operator_bytes": translation operator tables, "total_bytes":
+        planned device bytes of the handle} (mlfma_ops_memory)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_load().mlfma_ops_memory(self._h, ctypes.byref(a), ctypes.byref(b)),
+               "mlfma_ops_memory")
+        return {"operator_bytes": a.value, "total_bytes": b.value}
 
     def levels(self):
         nl = self.tree.info()["n_levels"]

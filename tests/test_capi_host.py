@@ -138,7 +138,7 @@ def test_precompute_argument_errors_and_memory_cap():
     assert lib.mlfma_precompute_operators(t.handle, -1.0, 3, 1, 0, ctypes.byref(h)) == G.EINVAL
     assert lib.mlfma_precompute_operators(t.handle, k, 0, 1, 0, ctypes.byref(h)) == G.EINVAL
     assert lib.mlfma_precompute_operators(t.handle, k, 3, 0, 0, ctypes.byref(h)) == G.EINVAL
-    assert lib.mlfma_precompute_operators(t.handle, k, 3, 1, 16, ctypes.byref(h)) == G.EINVAL
+    assert lib.mlfma_precompute_operators(t.handle, k, 3, 1, 32, ctypes.byref(h)) == G.EINVAL
     # leaves too small for the diagonal form: k sqrt(3) a < 1
     small = G.Tree(xyz, 0.05)
     assert lib.mlfma_precompute_operators(small.handle, k, 3, 1, 0, ctypes.byref(h)) == G.EINVAL
