@@ -374,7 +374,8 @@ hipError_t launch_pair(mlfma_ops_s *o, int l, int R, hipStream_t s, int down)
     DevLevel &P = o->lev[l], &C = o->lev[l + 1];
     return dev::pair_map(C.L, P.L, down != 0, down ? P.Lloc : C.S, down ? C.Lloc : P.S,
                          P.ptile[down], P.nptile[down], R, P.pfr[down][0], P.pfr[down][1],
-                         P.pfr[down][2], P.shift_axis, P.shift, s);
+                         P.pfr[down][2], P.shift_axis, P.shift, s,
+                         (o->flags & MLFMA_BF16X3_INTERP) != 0);
 }
 
 // One-pass interpolation / anterpolation of the level pair (l, l+1).
@@ -471,7 +472,9 @@ int autotune(mlfma_ops_s *o)
     const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
     for (int l = 3; l < o->n_lev && rc == MLFMA_OK; ++l) {
         DevLevel &P = o->lev[l];
-        if (!(P.onepass_ok || P.pair_ok[0] || P.pair_ok[1]) || b3) continue;
+        // (BF16x3: the three passes and the pair kernel; the one-pass
+        // kernels are FP32 only)
+        if (!((P.onepass_ok && !b3) || P.pair_ok[0] || P.pair_ok[1])) continue;
         // variant 0: three passes; 1 + k: one pass in work split k
         float bi = time_best(s, e0, e1, [&] { return launch_interp_staged(o, l, R, s); });
         float ba = time_best(s, e0, e1, [&] { return launch_anterp_staged(o, l, R, s); });
@@ -494,7 +497,7 @@ int autotune(mlfma_ops_s *o)
             }
         }
         if (rc != MLFMA_OK) break;
-        const int nsh = P.onepass_ok ? dev::pair_onepass_shapes(o->lev[l + 1].L, P.L) : 0;
+        const int nsh = (P.onepass_ok && !b3) ? dev::pair_onepass_shapes(o->lev[l + 1].L, P.L) : 0;
         for (int k = 0; k < nsh && rc == MLFMA_OK; ++k) {
             const float tf = time_best(s, e0, e1, [&] { return launch_interp_onepass(o, l, R, s, k); });
             const float af = time_best(s, e0, e1, [&] { return launch_anterp_onepass(o, l, R, s, k); });
@@ -903,8 +906,10 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 pl.add((int64_t)T.shift_axis.size() * 4);
                 pl.add(((int64_t)T.iF.size() + T.iA.size() + T.iG.size() + T.aF.size() +
                         T.aB.size() + T.aG.size()) * 4);
+                // pair kernel (BF16x3 fragments: up to 4x the FP32 ones)
                 pl.add(2 * (H.nbox + 1) * 8 + 2 * 4 * ((int64_t)T.iF.size() + T.iA.size() +
-                                                      T.iG.size() + 64 * 64));  // pair kernel
+                                                      T.iG.size() + 64 * 64) *
+                                                     ((flags & MLFMA_BF16X3_INTERP) ? 4 : 1));
                 const int64_t e = t->lev[l + 1].nbox * R * std::max(C.nth, T.nth) * T.Mc;
                 scratch = std::max(scratch, e);
             }
@@ -1244,8 +1249,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             P.interp_variant = use ? 1 : 0;
             P.anterp_variant = use ? 1 : 0;
         }
-        // fused pair kernel (FP32 path): parent groups and fragment tables
-        for (int l = 3; l < nl && !(flags & MLFMA_BF16X3_INTERP); ++l) {
+        // fused pair kernel (FP32 or BF16x3): parent groups and fragment tables
+        for (int l = 3; l < nl; ++l) {
             DevLevel &P = o->lev[l], &C = o->lev[l + 1];
             const LevelTables &T = o->tab[l];
             const HostLevel &H = t->lev[l];
@@ -1254,7 +1259,8 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
                 dev::PairTables pt;
                 if (dev::pair_tables(C.L, P.L, dn == 1, dn ? T.aF.data() : T.iF.data(),
                                      dn ? T.aB.data() : T.iA.data(),
-                                     dn ? T.aG.data() : T.iG.data(), &pt))
+                                     dn ? T.aG.data() : T.iG.data(), &pt,
+                                     (flags & MLFMA_BF16X3_INTERP) != 0))
                     return fail(MLFMA_EINVAL, "precompute: pair tables of level %d", l);
                 // runs of whole parents with at most max_children (8)
                 // children, each described by two int4 (see pair_map)

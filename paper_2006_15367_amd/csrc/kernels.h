@@ -81,10 +81,11 @@ struct PairTables {
 };
 bool pair_kernel_fits(int Lc, int Lp, bool down);
 int pair_tables(int Lc, int Lp, bool down, const float *F, const float *A, const float *G,
-                PairTables *t);
+                PairTables *t, bool bf16x3 = false);
 hipError_t pair_map(int Lc, int Lp, bool down, const float2 *In, float2 *Out, const int4 *desc,
                     int64_t ngroups, int R, const float *fr1, const float *fr2, const float *fr3,
-                    const float2 *shift_axis, const float2 *shift, hipStream_t st);
+                    const float2 *shift_axis, const float2 *shift, hipStream_t st,
+                    bool bf16x3 = false);
 
 bool pair_onepass_fits(int Lc, int Lp);
 int pair_onepass_shapes(int Lc, int Lp);

@@ -190,23 +190,46 @@ def test_deep_every_interpolation_form(c2, variant):
         assert forced == [(l, k) for l in range(3, nl) for k in ("interp", "anterp")]
 
 
-def test_deep_bf16x3_levels(c2):
-    """BF16 split-precision interpolation at full depth.  A split operand
-    hi + lo carries 16 significand bits and the dropped lo * lo product is
-    2^-16 of the full one, so each of the three maps of a level pair is
-    good to about 2^-16 = 1.5e-5; twelve maps from the leaf to level 3,
-    added coherently, give 1.8e-4: bound 2e-4 on the multipoles.  The
-    potential within 1e-3 of the FP64 oracle (the 3-digit target)."""
+@pytest.mark.parametrize("form", ["autotuned", "three_pass", "pair"])
+def test_deep_bf16x3_levels(c2, form):
+    """BF16 split-precision interpolation at full depth, with the autotuned
+    forms, three passes forced everywhere, or the BF16x3 pair kernel forced
+    on every level pair and direction that has it.  A split operand hi + lo
+    carries 16 significand bits and the dropped lo * lo product is 2^-16 of
+    the full one, so each of the three maps of a level pair is good to
+    about 2^-16 = 1.5e-5; twelve maps from the leaf to level 3, added
+    coherently, give 1.8e-4: bound 2e-4 on the multipoles.  Locals: the
+    FP32 M2L bound (1e-4) plus the anterpolation maps down to the level
+    (at most twelve, 1.8e-4): 3e-4.  The potential within 1e-3 of the FP64
+    oracle (the 3-digit target)."""
     G, torch = c2["G"], c2["torch"]
-    say("deep: bf16x3 operators")
+    say("deep: bf16x3 operators,", form)
     ops = G.Operators(c2["gt"], K, W.DIGITS, max_rhs=1, bf16x3=True)
+    nl = c2["ot"].n_lev
+    forced = []
+    if form != "autotuned":
+        for l in range(3, nl):
+            for k in ("interp", "anterp"):
+                try:
+                    ops.set_variant(l, 0 if form == "three_pass" else 4, kernel=k)
+                    forced.append((l, k))
+                except G.MlfmaError as e:
+                    assert e.status == G.EINVAL
+        say("deep bf16x3: forced on", forced)
+        if form == "pair":
+            assert (nl - 1, "interp") in forced and (nl - 1, "anterp") in forced
+    say("deep bf16x3: forms", ops.variants("interp"), ops.variants("anterp"))
     phi = _matvec(c2, c2["q"], ops=ops)
-    for l in range(3, c2["ot"].n_lev + 1):
+    for l in range(3, nl + 1):
         S = ops.copy_spectra(l, 0).cpu().numpy()
+        Lg = ops.copy_spectra(l, 1).cpu().numpy()
         torch.cuda.synchronize()
-        e = rel_l2(S, c2["inter"]["S"][l])
-        say("deep bf16x3: level", l, "S rel %.2e" % e)
-        assert e < 2e-4
+        es, ms = rel_l2(S, c2["inter"]["S"][l]), max_rel(S, c2["inter"]["S"][l])
+        el, ml = rel_l2(Lg, c2["inter"]["L"][l]), max_rel(Lg, c2["inter"]["L"][l])
+        say("deep bf16x3 %s: level %d S rel %.2e max %.2e | L rel %.2e max %.2e" % (
+            form, l, es, ms, el, ml))
+        assert es < 2e-4 and ms < 2e-4
+        assert el < 3e-4 and ml < 3e-4
     e = rel_l2(phi, c2["ophi"])
     say("deep bf16x3: potential vs FP64 MLFMA", e)
     assert e < 1e-3
