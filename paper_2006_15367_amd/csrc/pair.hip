@@ -515,7 +515,12 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
             d1 = desc[2 * g + 1];
         }
     };
-    float2 xv[S::XR], xs[DOWN ? S::XR : 1];
+    // LEAN (L2L with two K blocks in s1, the pair 13 -> 20): the octant's
+    // shift is formed from the axis factors in LDS at staging rather than
+    // prefetched, and the child locals are read in s3 next to their use, to
+    // stay within 256 registers; the other shapes prefetch both
+    constexpr bool LEAN = DOWN && B::KB1 > 1;
+    float2 xv[S::XR], xs[(DOWN && !LEAN) ? S::XR : 1];
     auto load_input = [&](int64_t t, const int4 &d0, const int4 &d1) {
         if (t >= ntiles) return;
         const int r = (int)(t % R);
@@ -528,7 +533,8 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
                 const int b = DOWN ? d0.x + ((d1.z >> (3 * sl)) & 7) : d0.y + sl;
                 xv[u] = In[((int64_t)b * R + r) * S::KI + q];
                 // L2L: the octant's shift on the parent grid, with the input
-                if constexpr (DOWN) xs[u] = shift[(int64_t)((d1.x >> (3 * sl)) & 7) * S::KI + q];
+                if constexpr (DOWN && !LEAN)
+                    xs[u] = shift[(int64_t)((d1.x >> (3 * sl)) & 7) * S::KI + q];
             }
         }
     };
@@ -573,8 +579,12 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
                 float2 v = make_float2(0.f, 0.f);
                 if (sl < nb) {
                     v = xv[u];
-                    if constexpr (DOWN) {
+                    if constexpr (LEAN) {
                         // conj(shift) * parent local
+                        const float2 sc = octant_shift(EX, EY, EZ, (octs >> (3 * sl)) & 7, th, q,
+                                                       true);
+                        v = make_float2(sc.x * v.x - sc.y * v.y, sc.x * v.y + sc.y * v.x);
+                    } else if constexpr (DOWN) {
                         const float2 sv = xs[u];
                         v = make_float2(sv.x * v.x + sv.y * v.y, sv.x * v.y - sv.y * v.x);
                     }
@@ -587,10 +597,11 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
         load_input(t + G, dB, eB);
         // L2L: the child locals this wave adds to in s3 (unit u = wave +
         // j NW is (slot, block of 8 output theta rows)), requested now so
-        // that s1 and s2 hide their latency
+        // that s1 and s2 hide their latency (LEAN: read in s3)
         constexpr int UPW3 = DOWN ? cdiv(S::NB * S::RT3, S::NW) : 1;
-        float2 old[UPW3][S::CT3][2];
-        if constexpr (DOWN) {
+        constexpr int UPW3E = (DOWN && !LEAN) ? UPW3 : 1;
+        float2 old[UPW3E][S::CT3][2];
+        if constexpr (DOWN && !LEAN) {
 #pragma unroll
             for (int j = 0; j < UPW3; ++j) {
                 const int u = wave + j * S::NW;
@@ -744,18 +755,31 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
                 const int i = u / S::RT3, rt = u - i * S::RT3;
                 if (i >= nb) continue;
                 const bool ra = rt * 8 + (lr >> 1) < S::TO;
+                float2 *o = Out + ((int64_t)(cb + i) * R + r) * S::KO;
+                float2 late[S::CT3][2];
+                if constexpr (LEAN) {
+#pragma unroll
+                    for (int ct = 0; ct < S::CT3; ++ct)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int to = rt * 8 + 2 * lq + h, po = ct * 16 + lr;
+                            late[ct][h] = (to < S::TO && po < S::PO) ? o[to * S::PO + po]
+                                                                    : make_float2(0.f, 0.f);
+                        }
+                }
                 f4 d[S::CT3];
                 synth(i, rt, ra, d);
-                float2 *o = Out + ((int64_t)(cb + i) * R + r) * S::KO;
 #pragma unroll
                 for (int ct = 0; ct < S::CT3; ++ct) {
                     const int po = ct * 16 + lr;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const int to = rt * 8 + 2 * lq + h;
-                        if (to < S::TO && po < S::PO)
-                            o[to * S::PO + po] = make_float2(old[j][ct][h].x + d[ct][2 * h],
-                                                             old[j][ct][h].y + d[ct][2 * h + 1]);
+                        if (to < S::TO && po < S::PO) {
+                            const float2 ov = LEAN ? late[ct][h] : old[LEAN ? 0 : j][ct][h];
+                            o[to * S::PO + po] = make_float2(ov.x + d[ct][2 * h],
+                                                             ov.y + d[ct][2 * h + 1]);
+                        }
                     }
                 }
             }
