@@ -428,13 +428,17 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * parent ranges balanced by record count and parents handed out dynamically,
  * 6 as 5 with a 32-sample operator slice (two workgroups per CU), 7 as 5
  * on antipodal slices (T_{-d}(k) = T_d(-k): the operators of one offset of
- * each +-pair in LDS, two workgroups per CU); 6 and 7 serve one RHS, calls
- * with several RHS run 5.
+ * each +-pair in LDS, two workgroups per CU), 8 as 5 on octant slices (the
+ * operators of the offsets (|dx|, |dy|, |dz|) in LDS, reflections as lane
+ * permutations); 6, 7 and 8 serve one RHS, calls with several RHS run 5.
+ * With MLFMA_SAMPLED_OPERATORS only 3, 4 and 5 exist.
  * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
  * and l+1, -1 on the leaf level and above level 3): 0 three passes through
  * HBM (ids _S1.._S3), 1 + k one pass with the intermediates in LDS in work
  * split k (children per item, waves per workgroup; 3 splits for the bands
- * 8 -> 13, 2 for 13 -> 20).
+ * 8 -> 13, 2 for 13 -> 20; FP32 only), 4 the fused pair kernel (the maps,
+ * shift and sibling sum or add in one launch; bands 8 -> 13 and 13 -> 20,
+ * FP32 or BF16x3).
  * kernel = MLFMA_K_P2P (the concurrent schedule; two entries): out[0]
  * where it forks the near field, 1 at the start of the matvec, 2 after C2M,
  * 0 at the start of the downward pass; out[1] the eighths of the CUs the
@@ -446,8 +450,10 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
 int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
 /* Diagnostics: force a variant of `kernel` on `level` (3..n_levels; for the
  * interpolation ids 3..n_levels-1); used by the tests to check every
- * variant.  EINVAL for an unknown variant, or for the one-pass variant where
- * its LDS plan does not fit or MLFMA_BF16X3_INTERP is set. */
+ * variant.  EINVAL for an unknown variant, for the one-pass variant where
+ * its LDS plan does not fit or MLFMA_BF16X3_INTERP is set, for the pair
+ * kernel where the level pair has none, and for M2L forms other than 3, 4
+ * and 5 with MLFMA_SAMPLED_OPERATORS. */
 int mlfma_ops_set_variant(mlfma_ops_t ops, int kernel, int level, int variant);
 
 /*
