@@ -442,7 +442,7 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * kernel = MLFMA_K_P2P (the concurrent schedule; two entries): out[0]
  * where it forks the near field, 1 at the start of the matvec, 2 after C2M,
  * 0 at the start of the downward pass; out[1] the eighths of the CUs the
- * M2L workgroups of levels above 3 may hold (4 or 6 from the precompute
+ * M2L workgroups of levels above 3 may hold (4, 6, 7 or 8 from the precompute
  * timing); both -1 when every kernel runs on the caller's stream.
  * mlfma_ops_set_variant with this kernel sets the fork point (level != 1,
  * variant 0..2) or the M2L share (level 1, variant 1..8).

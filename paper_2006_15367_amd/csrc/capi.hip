@@ -672,8 +672,11 @@ int tune_schedule(mlfma_ops_s *o)
                 reps = std::max(3, std::min(20, (int)(10.f / t1)));
         }
     }
-    for (int cfg = 0; cfg < 6 && rc == MLFMA_OK; ++cfg) {
-        const int mode = cfg % 3, share = cfg < 3 ? 6 : 4;
+    // M2L shares of 4/8 .. 8/8 of the CUs (8: uncapped) x the three fork
+    // points of the near field
+    constexpr int kShares[4] = {8, 7, 6, 4};
+    for (int cfg = 0; cfg < 12 && rc == MLFMA_OK; ++cfg) {
+        const int mode = cfg % 3, share = kShares[cfg / 3];
         o->near_fork = mode;
         o->m2l_share8 = share;
         rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
