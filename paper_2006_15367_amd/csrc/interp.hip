@@ -438,6 +438,24 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short &hi, unsigned
     lo = bf16_bits_rn(x - bf16_bits_to_float(hi));
 }
 
+// four values split at once: hi and lo as 4 packed bf16 each (one 8-byte
+// LDS store per plane; gfx950 converts pairs)
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void split_bf16x4(const float (&x)[4], uint2 &h, uint2 &l)
+{
+    bf16x4 hb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) hb[e] = (__bf16)x[e];
+    const uint2 hu = __builtin_bit_cast(uint2, hb);
+    bf16x4 lb;
+    lb[0] = (__bf16)(x[0] - __uint_as_float(hu.x << 16));
+    lb[1] = (__bf16)(x[1] - __uint_as_float(hu.x & 0xffff0000u));
+    lb[2] = (__bf16)(x[2] - __uint_as_float(hu.y << 16));
+    lb[3] = (__bf16)(x[3] - __uint_as_float(hu.y & 0xffff0000u));
+    h = hu;
+    l = __builtin_bit_cast(uint2, lb);
+}
+
 template <class P, int NT>
 __global__ void __launch_bounds__(256) k_rowgemm_bf16x3(P p, int col_override)
 {
@@ -479,31 +497,30 @@ __global__ void __launch_bounds__(256) k_rowgemm_bf16x3(P p, int col_override)
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int64_t rbase = tile * 32;
             __syncthreads();
+            // the tile's 32 complex rows as hi/lo planes: each thread takes
+            // 4 consecutive k of one row (real and imaginary rows 2t, 2t + 1)
             if (P::rows_fast) {
-                for (int base = threadIdx.x; base < 32 * K32; base += 4 * blockDim.x) {
-                    float2 v[4];
-                    int rl_[4], k_[4];
+                // rows fastest across threads (consecutive rows are
+                // contiguous in memory for a fixed k)
+                const int rl = threadIdx.x & 31;
+                const int64_t row = rbase + rl;
+                const bool ok = row < p.nrows;
+                for (int k0 = 4 * (threadIdx.x >> 5); k0 < K32; k0 += 4 * (blockDim.x >> 5)) {
+                    float re[4], im[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int idx = base + u * blockDim.x;
-                        const int k = idx >> 5, rl = idx & 31;
-                        rl_[u] = idx < 32 * K32 ? rl : -1;
-                        k_[u] = k;
-                        const int64_t row = rbase + rl;
-                        v[u] = (rl_[u] >= 0 && row < p.nrows && k < K) ? p.a(row, k)
-                                                                        : make_float2(0.f, 0.f);
+                    for (int e = 0; e < 4; ++e) {
+                        const float2 v = (ok && k0 + e < K) ? p.a(row, k0 + e)
+                                                            : make_float2(0.f, 0.f);
+                        re[e] = v.x;
+                        im[e] = v.y;
                     }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (rl_[u] < 0) continue;
-                        unsigned short h, l;
-                        split_bf16(v[u].x, h, l);
-                        Ah[(2 * rl_[u]) * KP + k_[u]] = h;
-                        Al[(2 * rl_[u]) * KP + k_[u]] = l;
-                        split_bf16(v[u].y, h, l);
-                        Ah[(2 * rl_[u] + 1) * KP + k_[u]] = h;
-                        Al[(2 * rl_[u] + 1) * KP + k_[u]] = l;
-                    }
+                    uint2 h, l;
+                    split_bf16x4(re, h, l);
+                    *(uint2 *)(Ah + (2 * rl) * KP + k0) = h;
+                    *(uint2 *)(Al + (2 * rl) * KP + k0) = l;
+                    split_bf16x4(im, h, l);
+                    *(uint2 *)(Ah + (2 * rl + 1) * KP + k0) = h;
+                    *(uint2 *)(Al + (2 * rl + 1) * KP + k0) = l;
                 }
             } else {
                 // 8 threads per row, row decoded once
@@ -511,15 +528,22 @@ __global__ void __launch_bounds__(256) k_rowgemm_bf16x3(P p, int col_override)
                 const int64_t row = rbase + rl;
                 const bool ok = row < p.nrows;
                 const typename P::Row w = p.row_at(ok ? row : 0);
-                for (int k = threadIdx.x & 7; k < K32; k += 8) {
-                    const float2 v = (ok && k < K) ? p.at(w, k) : make_float2(0.f, 0.f);
-                    unsigned short h, l;
-                    split_bf16(v.x, h, l);
-                    Ah[(2 * rl) * KP + k] = h;
-                    Al[(2 * rl) * KP + k] = l;
-                    split_bf16(v.y, h, l);
-                    Ah[(2 * rl + 1) * KP + k] = h;
-                    Al[(2 * rl + 1) * KP + k] = l;
+                for (int k0 = 4 * (threadIdx.x & 7); k0 < K32; k0 += 32) {
+                    float re[4], im[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float2 v = (ok && k0 + e < K) ? p.at(w, k0 + e)
+                                                            : make_float2(0.f, 0.f);
+                        re[e] = v.x;
+                        im[e] = v.y;
+                    }
+                    uint2 h, l;
+                    split_bf16x4(re, h, l);
+                    *(uint2 *)(Ah + (2 * rl) * KP + k0) = h;
+                    *(uint2 *)(Al + (2 * rl) * KP + k0) = l;
+                    split_bf16x4(im, h, l);
+                    *(uint2 *)(Ah + (2 * rl + 1) * KP + k0) = h;
+                    *(uint2 *)(Al + (2 * rl + 1) * KP + k0) = l;
                 }
             }
             __syncthreads();
