@@ -283,7 +283,7 @@ def test_concurrent_schedule_equals_one_stream(c1):
     Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
     Qd = torch.from_numpy(Q).cuda()
     tuned, share = ops.variants("p2p")
-    assert tuned in (0, 1, 2) and share in (4, 6) and ops1.variants("p2p") == [-1, -1]
+    assert tuned in (0, 1, 2) and share in (4, 6, 7, 8) and ops1.variants("p2p") == [-1, -1]
     try:
         # near field forked at the downward pass / start / after C2M; M2L
         # of levels > 3 on half, three quarters or all of the CUs
