@@ -489,6 +489,14 @@ int mlfma_fft_execute(mlfma_fft_t p, const void *in, void *out, int64_t nitems, 
     if (nitems < 0) return fail(MLFMA_EINVAL, "fft_execute: nitems %lld < 0", (long long)nitems);
     if (nitems == 0) return MLFMA_OK;
     if (!in || !out) return fail(MLFMA_EINVAL, "fft_execute: null buffer");
+    {
+        // the batch is read and written by different workgroups: in and out
+        // must not overlap
+        const uintptr_t i0 = (uintptr_t)in, o0 = (uintptr_t)out;
+        const uintptr_t i1 = i0 + (uintptr_t)nitems * p->desc.ti * p->desc.pi * sizeof(float2);
+        const uintptr_t o1 = o0 + (uintptr_t)nitems * p->desc.to * p->desc.po * sizeof(float2);
+        if (i0 < o1 && o0 < i1) return fail(MLFMA_EINVAL, "fft_execute: in and out overlap");
+    }
     const int64_t nblk = (nitems + p->desc.ipw - 1) / p->desc.ipw;
     if (nblk > 0x7fffffffll) return fail(MLFMA_EINVAL, "fft_execute: batch too large");
     int cur = 0;

@@ -118,3 +118,16 @@ def test_fft_empty_batch_is_a_noop():
     y = r(x)
     torch.cuda.synchronize()
     assert tuple(y.shape) == (0, 14, 28)
+
+
+def test_fft_overlapping_buffers_rejected():
+    torch = cuda_or_skip()
+    from paper_2006_15367_amd import mlfma as G
+    r = G.FFTResampler(8, 18, 18)
+    x = torch.zeros((4, 9, 18), dtype=torch.complex64, device="cuda")
+    with pytest.raises(G.MlfmaError) as e:
+        r(x, out=x)
+    assert e.value.status == G.EINVAL
+    y = r(x)
+    torch.cuda.synchronize()
+    assert tuple(y.shape) == (4, 9, 18)
