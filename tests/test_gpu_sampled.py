@@ -126,3 +126,45 @@ def test_sampled_spheroid_vs_exact_tables_and_dense(oracle_dense):
     idx = rng.choice(xyz.shape[0], 256, replace=False)
     ref = oracle_dense.potential(xyz, q.astype(np.complex128), K, tgt=xyz[idx])
     assert rel_l2(phi[idx], ref) < 1e-3
+
+
+def test_sampled_with_bf16x3_adjoint_and_field():
+    """The sampled operators with the other options on the 4k sphere: three
+    right-hand sides with BF16x3 interpolation against the exact-table FP32
+    handle, the adjoint through the dot-product identity, the field against
+    the exact-table field.  The BF16x3 maps leave about 1.5e-5 on the
+    spectra (full-depth test), which the leaf evaluation amplifies on the
+    potential (its quadrature sum is much smaller than its terms): about
+    2e-4 there against the FP64 oracle; bound: the method's 3-digit target,
+    1e-3."""
+    torch = cuda_or_skip()
+    from paper_2006_15367_amd import mlfma as G
+    xyz, q = W.make("sphere4k")
+    rng = np.random.default_rng(73)
+    n = xyz.shape[0]
+    Q = (rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))).astype(np.complex64)
+    gt = G.Tree(xyz, W.LEAF_SIZE)
+    ops = G.Operators(gt, K, W.DIGITS, max_rhs=3, sampled=True, bf16x3=True)
+    ref = G.Operators(gt, K, W.DIGITS, max_rhs=3)
+    Qd = torch.from_numpy(Q).cuda()
+    P, Pr = ops.matvec(Qd), ref.matvec(Qd)
+    V = torch.from_numpy(np.ascontiguousarray(Q[:, ::-1])).cuda()
+    A = ops.adjoint(V)
+    F, Fr = ops.field(Qd[:, 0].contiguous()), ref.field(Qd[:, 0].contiguous())
+    torch.cuda.synchronize()
+    P, Pr, A = P.cpu().numpy(), Pr.cpu().numpy(), A.cpu().numpy()
+    F, Fr = F.cpu().numpy(), Fr.cpu().numpy()
+    e = rel_l2(P, Pr)
+    say("sampled + bf16x3, 3 RHS: vs exact-table FP32 %.2e" % e)
+    assert e < 1e-3
+    # (with BF16x3 the data are split to about 16 significand bits per map,
+    # so the discrete operator is linear, and its adjoint exact, only to
+    # about 2^-16 per map: bound 1e-4 of |v| |A q|)
+    Vn = V.cpu().numpy()
+    for r in range(3):
+        lhs = np.vdot(Vn[:, r], P[:, r])
+        rhs = np.vdot(A[:, r], Q[:, r])
+        assert abs(lhs - rhs) <= 1e-4 * np.linalg.norm(Vn[:, r]) * np.linalg.norm(P[:, r])
+    ef = rel_l2(F, Fr)
+    say("sampled + bf16x3: field vs exact-table FP32 %.2e" % ef)
+    assert ef < 1e-3
