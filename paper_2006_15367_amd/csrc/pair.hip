@@ -520,8 +520,9 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
     // prefetched, and the child locals are read in s3 next to their use, to
     // stay within 256 registers; the other shapes prefetch both
     constexpr bool LEAN = DOWN && B::KB1 > 1;
-    float2 xv[S::XR], xs[(DOWN && !LEAN) ? S::XR : 1];
+    float2 xv[LEAN ? 1 : S::XR], xs[(DOWN && !LEAN) ? S::XR : 1];
     auto load_input = [&](int64_t t, const int4 &d0, const int4 &d1) {
+        if constexpr (LEAN) return;  // (LEAN: read at staging)
         if (t >= ntiles) return;
         const int r = (int)(t % R);
         const int nb = d0.z;
@@ -578,7 +579,12 @@ k_pair_bf(const float2 *__restrict__ In, float2 *__restrict__ Out, const int4 *_
             if (sl < S::NB) {
                 float2 v = make_float2(0.f, 0.f);
                 if (sl < nb) {
-                    v = xv[u];
+                    if constexpr (LEAN) {
+                        const int b = dA.x + ((eA.z >> (3 * sl)) & 7);
+                        v = In[((int64_t)b * R + r) * S::KI + q];
+                    } else {
+                        v = xv[u];
+                    }
                     if constexpr (LEAN) {
                         // conj(shift) * parent local
                         const float2 sc = octant_shift(EX, EY, EZ, (octs >> (3 * sl)) & 7, th, q,
