@@ -88,7 +88,7 @@ enum mlfma_flags {
                                 per distinct offset length, T at 8 L + 1
                                 angles to the offset; M2L interpolates its
                                 operators (10-point Lagrange, relative error
-                                below 3e-8) into LDS; M2L forms 3, 4 and 5
+                                below 3e-8) into LDS; M2L forms 3, 4, 5 and 9
                                 only */
 };
 
@@ -430,8 +430,12 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * on antipodal slices (T_{-d}(k) = T_d(-k): the operators of one offset of
  * each +-pair in LDS, two workgroups per CU), 8 as 5 on octant slices (the
  * operators of the offsets (|dx|, |dy|, |dz|) in LDS, reflections as lane
- * permutations); 6, 7 and 8 serve one RHS, calls with several RHS run 5.
- * With MLFMA_SAMPLED_OPERATORS only 3, 4 and 5 exist.
+ * permutations); 6, 7 and 8 serve one RHS, calls with several RHS run 5;
+ * 9 as 5 on the matrix cores for several RHS (per sample, the parent's
+ * children in pairs x four right-hand sides accumulate operator x source
+ * over the records on v_mfma_f32_4x4x1f32; at one RHS 3/4 of its tiles
+ * are idle, and the precompute timing leaves it out there).  With
+ * MLFMA_SAMPLED_OPERATORS only 3, 4, 5 and 9 exist.
  * kernel = MLFMA_K_INTERP or MLFMA_K_ANTERP (entry l = the pair of levels l
  * and l+1, -1 on the leaf level and above level 3): 0 three passes through
  * HBM (ids _S1.._S3), 1 + k one pass with the intermediates in LDS in work
@@ -452,8 +456,8 @@ int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entrie
  * interpolation ids 3..n_levels-1); used by the tests to check every
  * variant.  EINVAL for an unknown variant, for the one-pass variant where
  * its LDS plan does not fit or MLFMA_BF16X3_INTERP is set, for the pair
- * kernel where the level pair has none, and for M2L forms other than 3, 4
- * and 5 with MLFMA_SAMPLED_OPERATORS. */
+ * kernel where the level pair has none, and for M2L forms other than 3, 4,
+ * 5 and 9 with MLFMA_SAMPLED_OPERATORS. */
 int mlfma_ops_set_variant(mlfma_ops_t ops, int kernel, int level, int variant);
 
 /*

@@ -54,7 +54,7 @@ struct DevLevel {
                                      // 3 sibling groups with per-source records, 4 = 3 with
                                      // the slice-major sweep, 5 = 3 record-balanced, 6 = 5 on
                                      // 32-sample slices, 7 = 5 on antipodal slices, 8 = 5 on
-                                     // octant slices
+                                     // octant slices, 9 = 3 on the matrix cores (several RHS)
     int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     // antipodal slices (one-RHS variant 7): operators of one offset of each
@@ -319,6 +319,10 @@ int refresh_positions(mlfma_ops_s *o)
     return MLFMA_OK;
 }
 
+// M2L forms that run on sampled operators (the record kernels that stage
+// the operator slice themselves)
+bool sampled_m2l_form(int v) { return (v >= 3 && v <= 5) || v == 9; }
+
 // ---------------------------------------------------------------- matvec --
 // max_wg: workgroup cap of the record variants (0: one per CU)
 hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, int max_wg = 0)
@@ -326,8 +330,8 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
     DevLevel &D = o->lev[l];
     DevLevel &Pl = o->lev[l - 1];
     if (o->sampled) {
-        // record kernel with the operator slice interpolated from the tables
-        if (variant < 3 || variant > 5) return hipErrorInvalidValue;
+        // record kernels with the operator slice interpolated from the tables
+        if (!sampled_m2l_form(variant)) return hipErrorInvalidValue;
         dev::SampledT st;
         st.tab = D.Tsamp;
         st.xr = D.xr;
@@ -335,10 +339,16 @@ hipError_t launch_m2l(mlfma_ops_s *o, int l, int variant, int R, hipStream_t s, 
         st.nth = D.nth;
         st.nph = D.nph;
         st.M = D.Msamp;
+        if (variant == 9)
+            return dev::m2l_mfma(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
+                                 D.rec_off, nullptr, D.S, R, D.Lloc, s, max_wg, st);
         return dev::m2l_rec(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
                             D.rec_off, nullptr, D.S, R, D.Lloc, s, variant - 3, max_wg, st);
     }
     switch (variant) {
+    case 9:
+        return dev::m2l_mfma(Pl.nbox, D.K, D.ntypes, Pl.child_start, D.rec_start, D.rec_src,
+                             D.rec_off, D.T, D.S, R, D.Lloc, s, max_wg);
     case 1:
         return dev::m2l_lds(D.nbox, D.K, D.ntypes, D.far_start, D.far_src, D.far_type, D.T, D.S,
                             R, D.Lloc, s);
@@ -454,9 +464,10 @@ int autotune(mlfma_ops_s *o)
     for (int l = 3; l <= o->n_lev && rc == MLFMA_OK; ++l) {
         float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < 9; ++v) {
-            if (v >= 6 && R != 1) continue;  // variants 6, 7 and 8 serve one RHS
-            if (o->sampled && (v < 3 || v > 5)) continue;  // forms with sampled operators
+        for (int v = 0; v < 10; ++v) {
+            if (v >= 6 && v <= 8 && R != 1) continue;  // variants 6, 7 and 8 serve one RHS
+            if (v == 9 && R == 1) continue;  // the matrix-core form needs several RHS
+            if (o->sampled && !sampled_m2l_form(v)) continue;
             const float t = time_best(s, e0, e1, [&] { return launch_m2l(o, l, v, R, s); });
             if (t < 0.f) {
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
@@ -1819,8 +1830,8 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
     if (!o) return fail(MLFMA_EINVAL, "ops_set_variant: ops is NULL");
     if (kernel == MLFMA_K_M2L) {
         if (level < 3 || level > o->n_lev) return fail(MLFMA_EINVAL, "ops_set_variant: bad level %d", level);
-        if (variant < 0 || variant > 8) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
-        if (o->sampled && (variant < 3 || variant > 5))
+        if (variant < 0 || variant > 9) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+        if (o->sampled && !sampled_m2l_form(variant))
             return fail(MLFMA_EINVAL, "ops_set_variant: M2L form %d needs full operator tables",
                         variant);
         o->lev[level].m2l_variant = variant;

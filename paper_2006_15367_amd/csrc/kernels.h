@@ -160,6 +160,15 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
                    int schedule, int max_wg = 0, SampledT sampled = SampledT());
 
+// M2L on the matrix cores for several right-hand sides (variant 9): the
+// records and operator slices of m2l_rec; per sample, the parent's children
+// (in pairs) x the right-hand sides (in fours) accumulate operator x source
+// over the records on v_mfma_f32_4x4x1f32
+hipError_t m2l_mfma(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
+                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
+                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
+                    int max_wg = 0, SampledT sampled = SampledT());
+
 // M2L per observer with the operator slice in LDS
 hipError_t m2l_lds(int64_t nbox, int64_t K, int ntypes, const int32_t *far_start,
                    const int32_t *far_src, const int16_t *far_type, const float2 *T,

@@ -997,6 +997,206 @@ hipError_t m2l_rec(int64_t nparent, int64_t K, int ntypes, const int32_t *child_
     return hipGetLastError();
 }
 
+// Many right-hand sides on the matrix cores (variant 9).  For one sample k
+// the M2L of a parent's children is a small dense product over the parent's
+// source records, L[c][r] += sum_s T_{t(c,s)}[k] S[s][r].  A wave takes one
+// parent, 16 samples and 4 NQ right-hand sides; v_mfma_f32_4x4x1f32 computes
+// 16 independent 4x4 tiles, one per sample (block b = lane / 4, the sample
+// k0 + 16 sb + b): the rows of a child pair p (child 2p real, imaginary,
+// child 2p+1 real, imaginary; A from lane 4b + row), the columns four
+// right-hand sides (B from lane 4b + column, D column lane % 4, row = the
+// accumulator register).  Each source record takes two instructions per
+// (pair, RHS block), one per part of the source value:
+//   re += Tr Sr - Ti Si,  im += Ti Sr + Tr Si,
+// the operator values read from the LDS slice of the record kernels
+// (64 samples, the records' byte offsets), the source values from the
+// spectra.  The 16 waves of a workgroup are 4 sample blocks x 4 parent
+// streams over the workgroup's parent range; records one ahead in flight.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int NP, int NQ>
+__device__ __forceinline__ void m2l_mfma_parent(const char *Tsb, int lane, int toff, int e0,
+                                                int e1, const int32_t *__restrict__ rec_src,
+                                                const int32_t *__restrict__ rec_off,
+                                                const char *__restrict__ Sb, uint64_t sstride,
+                                                const uint32_t (&voff)[NQ],
+                                                floatx4 (&acc)[NQ][4])
+{
+    if (e1 <= e0) return;
+    const bool second = (lane & 2) != 0;  // the pair's second child
+    const bool imag = (lane & 1) != 0;    // imaginary row
+    float2 ta[NP], tb[NP], sa[NQ], sb[NQ];
+    auto fetch = [&](int e, float2 (&t)[NP], float2 (&v)[NQ]) {
+        const char *base = Sb + (uint64_t)(uint32_t)rec_src[e] * sstride;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = *(const float2 *)(base + voff[q]);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int o0 = rec_off[8 * (int64_t)e + 2 * p], o1 = rec_off[8 * (int64_t)e + 2 * p + 1];
+            t[p] = *(const float2 *)(Tsb + (second ? o1 : o0) + toff);
+        }
+    };
+    auto compute = [&](const float2 (&t)[NP], const float2 (&v)[NQ]) {
+        float a1[NP], a2[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            a1[p] = imag ? t[p].y : t[p].x;
+            a2[p] = imag ? t[p].x : -t[p].y;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                acc[q][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1[p], v[q].x, acc[q][p], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                acc[q][p] = __builtin_amdgcn_mfma_f32_4x4x1f32(a2[p], v[q].y, acc[q][p], 0, 0, 0);
+    };
+    // (the record after a list's last is the next list's first or one of
+    // the zero records appended after the last list: fetched, never used)
+    fetch(e0, ta, sa);
+    for (int e = e0;;) {
+        fetch(e + 1, tb, sb);
+        compute(ta, sa);
+        if (++e >= e1) break;
+        fetch(e + 1, ta, sa);
+        compute(tb, sb);
+        if (++e >= e1) break;
+    }
+}
+
+template <int NQ, bool SAMPLED>
+__global__ void __launch_bounds__(1024)
+k_m2l_mfma(int64_t nparent, int64_t K, int ntypes, const int32_t *__restrict__ child_start,
+           const int32_t *__restrict__ rec_start, const int32_t *__restrict__ rec_src,
+           const int32_t *__restrict__ rec_off, const float2 *__restrict__ T,
+           const float2 *__restrict__ S, int R, int nkc, int nrange, float2 *__restrict__ Lout,
+           SampledT sampled)
+{
+    extern __shared__ float2 Ts[];  // [ntypes + 1][64], row ntypes = 0
+    const int64_t w = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int kc = (int)(w % nkc);
+    const int64_t k0 = (int64_t)kc * 64;
+    if constexpr (SAMPLED)
+        stage_t_interp<64>(Ts, sampled, ntypes, K, k0);
+    else
+        stage_t_slice<64>(Ts, T, ntypes, K, k0);
+    for (int idx = threadIdx.x; idx < 64; idx += blockDim.x)
+        Ts[ntypes * 64 + idx] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const char *Tsb = (const char *)Ts;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sblk = wave & 3;  // 16-sample block
+    const int pstream = wave >> 2;
+    const int64_t k = k0 + 16 * sblk + (lane >> 2);
+    const bool kvalid = k < K;
+    const int64_t kk = kvalid ? k : K - 1;
+    const int toff = (16 * sblk + (lane >> 2)) * (int)sizeof(float2);
+    const int r0 = (int)blockIdx.z * 4 * NQ;
+    const uint64_t sstride = (uint64_t)R * (uint64_t)K * sizeof(float2);
+    uint32_t voff[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int r = r0 + 4 * q + (lane & 3);
+        // (a multiple of 8 below 2^31, as the mask states)
+        voff[q] = (uint32_t)(((int64_t)(r < R ? r : r0) * K + kk) * (int64_t)sizeof(float2)) &
+                  0x7ffffff8u;
+    }
+    const char *Sb = (const char *)S;
+    // parent range of the workgroup: equal record counts (binary search)
+    const int64_t total = rec_start[nparent];
+    const int64_t rg = w / nkc;
+    auto lower = [&](int64_t target) -> int64_t {
+        int64_t lo = 0, hi = nparent;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)__builtin_amdgcn_readfirstlane(rec_start[mid]) < target) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int64_t pbeg = rg == 0 ? 0 : lower(total * rg / nrange);
+    const int64_t pend = rg == nrange - 1 ? nparent : lower(total * (rg + 1) / nrange);
+    for (int64_t P = pbeg + pstream; P < pend; P += 4) {
+        const int o0 = __builtin_amdgcn_readfirstlane(child_start[P]);
+        const int no = __builtin_amdgcn_readfirstlane(child_start[P + 1]) - o0;
+        const int e0 = __builtin_amdgcn_readfirstlane(rec_start[P]);
+        const int e1 = __builtin_amdgcn_readfirstlane(rec_start[P + 1]);
+        floatx4 acc[NQ][4];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[q][p] = floatx4{0.f, 0.f, 0.f, 0.f};
+        switch ((no + 1) >> 1) {
+        case 1:
+            m2l_mfma_parent<1, NQ>(Tsb, lane, toff, e0, e1, rec_src, rec_off, Sb, sstride, voff, acc);
+            break;
+        case 2:
+            m2l_mfma_parent<2, NQ>(Tsb, lane, toff, e0, e1, rec_src, rec_off, Sb, sstride, voff, acc);
+            break;
+        case 3:
+            m2l_mfma_parent<3, NQ>(Tsb, lane, toff, e0, e1, rec_src, rec_off, Sb, sstride, voff, acc);
+            break;
+        case 4:
+            m2l_mfma_parent<4, NQ>(Tsb, lane, toff, e0, e1, rec_src, rec_off, Sb, sstride, voff, acc);
+            break;
+        default: break;
+        }
+        if (!kvalid) continue;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int r = r0 + 4 * q + (lane & 3);
+            if (r >= R) continue;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                if (2 * p < no)
+                    Lout[((int64_t)(o0 + 2 * p) * R + r) * K + k] =
+                        make_float2(acc[q][p][0], acc[q][p][1]);
+                if (2 * p + 1 < no)
+                    Lout[((int64_t)(o0 + 2 * p + 1) * R + r) * K + k] =
+                        make_float2(acc[q][p][2], acc[q][p][3]);
+            }
+        }
+    }
+}
+
+hipError_t m2l_mfma(int64_t nparent, int64_t K, int ntypes, const int32_t *child_start,
+                    const int32_t *rec_start, const int32_t *rec_src, const int32_t *rec_off,
+                    const float2 *T, const float2 *S, int R, float2 *Lout, hipStream_t s,
+                    int max_wg, SampledT sampled)
+{
+    if (nparent == 0 || K == 0) return hipSuccess;
+    const size_t lds = (size_t)(ntypes + 1) * 64 * sizeof(float2);
+    if (lds > 163840) return hipErrorInvalidValue;
+    if ((uint64_t)R * (uint64_t)K * sizeof(float2) > 0x7fffffffull) return hipErrorInvalidValue;
+    // right-hand sides per wave: 16, or 8 / 4 for fewer
+    const int NQ = R > 8 ? 4 : R > 4 ? 2 : 1;
+    const int nkc = (int)((K + 63) / 64);
+    const int nz = (R + 4 * NQ - 1) / (4 * NQ);
+    const int ncu = max_wg > 0 ? std::min(max_wg, cu_count()) : cu_count();
+    // one workgroup per CU (the LDS slice), at least 4 parents per range
+    const int nrange = (int)std::max<int64_t>(
+        1, std::min<int64_t>(ncu / std::max(1, nkc * nz), (nparent + 3) / 4));
+    const dim3 grid((unsigned)(nkc * nrange), 1, (unsigned)nz);
+#define M2L_MFMA(NQV, SV)                                                                        \
+    M2L_LAUNCH((k_m2l_mfma<NQV, SV>), grid, dim3(1024), lds, s, nparent, K, ntypes, child_start, \
+               rec_start, rec_src, rec_off, T, S, R, nkc, nrange, Lout, sampled)
+    if (sampled.tab) {
+        if (NQ == 4) M2L_MFMA(4, true);
+        else if (NQ == 2) M2L_MFMA(2, true);
+        else M2L_MFMA(1, true);
+    } else {
+        if (NQ == 4) M2L_MFMA(4, false);
+        else if (NQ == 2) M2L_MFMA(2, false);
+        else M2L_MFMA(1, false);
+    }
+#undef M2L_MFMA
+    return hipGetLastError();
+}
+
 hipError_t m2l(int64_t nbox, int64_t K, const int32_t *far_start, const int32_t *far_src,
                const int16_t *far_type, const float2 *T, const float2 *S, int R,
                float2 *Lout, hipStream_t s)

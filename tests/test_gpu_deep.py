@@ -130,7 +130,7 @@ def test_deep_vs_dense_sampled(c2, oracle_dense):
     assert e < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_deep_every_m2l_form_on_every_level(c2, variant):
     ops = c2["gops"]
     nl = c2["ot"].n_lev

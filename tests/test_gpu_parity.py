@@ -142,7 +142,7 @@ def test_field_vs_dense(c1):
     assert e < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_every_m2l_variant(c1, variant):
     torch = c1["torch"]
     say("c1: M2L variant", variant)
@@ -223,6 +223,45 @@ def test_bf16x3_interpolation_accuracy(c1):
     assert e_dense < 1e-3
     assert e_orc < 3e-4
     assert rel_l2(phi, fp32) < 3e-4
+
+
+def test_m2l_matrix_core_form_ragged_rhs(c1):
+    """M2L form 9 (matrix cores, right-hand sides in blocks of 16 per wave)
+    forced on every level with 20 right-hand sides (a full block and a
+    block of 4 of 16) against form 5 (the VALU record kernel) element by
+    element, and the first column's locals against the FP64 oracle.  The
+    two forms sum the same products in another order: FP32 rounding of the
+    far-field sums, bound 1e-5 of the largest value per level."""
+    torch = c1["torch"]
+    from paper_2006_15367_amd import mlfma as G
+    R = 20
+    ops = G.Operators(c1["gt"], K, W.DIGITS, max_rhs=R)
+    n = c1["xyz"].shape[0]
+    rng = np.random.default_rng(91)
+    Q = (rng.standard_normal((n, R)) + 1j * rng.standard_normal((n, R))).astype(np.complex64)
+    Q[:, 0] = c1["q"]
+    Qd = torch.from_numpy(Q).cuda()
+    nl = c1["ot"].n_lev
+    out = {}
+    for v in (5, 9):
+        for l in range(3, nl + 1):
+            ops.set_variant(l, v)
+        say("m2l form", v, "with", R, "rhs")
+        P = _run(c1, ops.matvec, Qd)
+        Ls = {l: ops.copy_spectra(l, 1, nrhs=R).cpu().numpy() for l in range(3, nl + 1)}
+        torch.cuda.synchronize()
+        out[v] = (P, Ls)
+    for l in range(3, nl + 1):
+        a, b = out[9][1][l], out[5][1][l]
+        e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        say("level", l, "form 9 vs 5: max rel", e)
+        assert e < 1e-5, l
+        L0 = a.reshape(a.shape[0], R, -1)[:, 0, :]
+        assert rel_l2(L0, c1["inter"]["L"][l].reshape(L0.shape)) < 1e-4, l
+    e = float(np.max(np.abs(out[9][0] - out[5][0])) / np.max(np.abs(out[5][0])))
+    say("potential form 9 vs 5: max rel", e)
+    assert e < 1e-5
+    assert rel_l2(out[9][0][:, 0], c1["ophi"]) < 1e-4
 
 
 def test_batched_64_rhs_equals_single():
@@ -341,7 +380,7 @@ def test_variant_and_schedule_limits(c1):
     nl = c1["ot"].n_lev
     before = (ops.variants("m2l"), ops.variants("p2p"))
     bad = [
-        (3, 9, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
+        (3, 10, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
         (0, 3, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
         (nl, 0, "interp"),
     ]

@@ -48,7 +48,9 @@ def test_sampled_sphere4k_levels_vs_oracle(oracle_dense):
     gt = G.Tree(xyz, W.LEAF_SIZE)
     ops = G.Operators(gt, K, W.DIGITS, sampled=True)
     say("sampled: sphere4k M2L forms", ops.variants("m2l"))
-    for v in (3, 4, 5):
+    # (form 9, the matrix-core form, runs here at one RHS: 3 of its 4
+    # right-hand-side columns idle)
+    for v in (3, 4, 5, 9):
         for l in range(3, ot.n_lev + 1):
             ops.set_variant(l, v)
         phi = _matvec(torch, ops, q)
