@@ -38,7 +38,8 @@ def _loss_and_grads(c):
     L = (phi - tt).abs().pow(2).sum()
     L.backward()
     torch.cuda.synchronize()
-    return (float(L), phi.detach().cpu().numpy(), q.grad.cpu().numpy(), x.grad.cpu().numpy())
+    return (float(L.detach()), phi.detach().cpu().numpy(), q.grad.cpu().numpy(),
+            x.grad.cpu().numpy())
 
 
 def test_grad_q_is_adjoint_of_residual(case):
