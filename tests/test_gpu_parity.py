@@ -264,6 +264,36 @@ def test_m2l_matrix_core_form_ragged_rhs(c1):
     assert rel_l2(out[9][0][:, 0], c1["ophi"]) < 1e-4
 
 
+def test_m2l_matrix_core_form_64_rhs():
+    """M2L form 9 at 64 right-hand sides (four blocks of 16 per sample
+    slice) on the 32,768-point sphere (6 levels), forced on every level,
+    against form 5 element by element: the same products summed in another
+    order, FP32 rounding, bound 1e-5 of the largest value per level."""
+    torch = cuda_or_skip()
+    from paper_2006_15367_amd import mlfma as G
+    xyz, Q = W.make("sphere262k_r64", n=32768)
+    tree = G.Tree(xyz, W.LEAF_SIZE)
+    nl = tree.info()["n_levels"]
+    ops = G.Operators(tree, K, W.DIGITS, max_rhs=64)
+    Qd = torch.from_numpy(Q).cuda()
+    out = {}
+    for v in (5, 9):
+        for l in range(3, nl + 1):
+            ops.set_variant(l, v)
+        say("m2l form", v, "at 64 rhs,", nl, "levels")
+        P = ops.matvec(Qd)
+        Ls = {l: ops.copy_spectra(l, 1, nrhs=64).cpu().numpy() for l in range(3, nl + 1)}
+        torch.cuda.synchronize()
+        out[v] = (P.cpu().numpy(), Ls)
+    for l in range(3, nl + 1):
+        a, b = out[9][1][l], out[5][1][l]
+        e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        say("level", l, "form 9 vs 5: max rel", e)
+        assert e < 1e-5, l
+    e = float(np.max(np.abs(out[9][0] - out[5][0])) / np.max(np.abs(out[5][0])))
+    assert e < 1e-5
+
+
 def test_batched_64_rhs_equals_single():
     """64 right-hand sides in one call equal 64 single-RHS calls.
 
