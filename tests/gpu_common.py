@@ -18,6 +18,13 @@ def cuda_or_skip():
     return torch
 
 
+def max_rel(a, b):
+    """Largest element deviation over the largest reference value."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 def rel_l2(a, b):
     a = np.asarray(a)
     b = np.asarray(b)

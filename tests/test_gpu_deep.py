@@ -22,7 +22,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import cuda_or_skip, rel_l2, say
+from gpu_common import cuda_or_skip, max_rel, rel_l2, say
 
 from paper_2006_15367_amd import workloads as W
 
@@ -32,10 +32,6 @@ K = W.K_WAVENUMBER
 TOL_S = 1e-5
 TOL_L = 1e-4
 
-
-def max_rel(a, b):
-    """Largest element deviation over the largest reference value."""
-    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
 
 
 @pytest.fixture(scope="module")

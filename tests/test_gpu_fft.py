@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.special as sp
 
-from gpu_common import cuda_or_skip, say
+from gpu_common import cuda_or_skip, max_rel, say
 
 from oracle import fft_interp as F
 
@@ -21,9 +21,6 @@ pytestmark = pytest.mark.gpu
 
 TOL = 2e-6
 
-
-def max_rel(a, b):
-    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
 def _run(torch, G, lb, pi, po, ant, X):

@@ -14,7 +14,7 @@ FP64 oracle, 1e-3 against the dense definition.
 import numpy as np
 import pytest
 
-from gpu_common import cuda_or_skip, rel_l2, say
+from gpu_common import cuda_or_skip, max_rel, rel_l2, say
 
 from paper_2006_15367_amd import workloads as W
 
@@ -23,9 +23,6 @@ pytestmark = pytest.mark.gpu
 K = W.K_WAVENUMBER
 TOL = 1e-4
 
-
-def max_rel(a, b):
-    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
 
 
 def _matvec(torch, ops, q):
