@@ -490,8 +490,12 @@ def main():
         torch.cuda.synchronize()
         # ten profiled (eager) steps, every kernel timed alone: per-phase
         # times and the dominant kernel
+        # (128 launches a step: more than any workload's matvec makes, and
+        # few enough events that creating them leaves the timed steps alone;
+        # 4096 a step, 82k events created and destroyed right before the
+        # timed region, slowed it by about 5 us a step)
         n_prof = 10
-        ops.profile_begin(None, 4096 * n_prof, serial=True)
+        ops.profile_begin(None, 128 * n_prof, serial=True)
         for _ in range(n_prof):
             ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
@@ -501,21 +505,27 @@ def main():
 
         # timed region: K steps.  Eager mode times the dominant kernel's
         # launches with HIP events inside the timed region, in its last
-        # quarter of the steps (the events the launches record cost about
-        # 3 us per launch, kept off the other three quarters); graph mode
-        # times them in an equal number of eager steps right after it.
-        n_ev = max(1, args.steps // 4)
+        # tenth of the steps (a step whose launches record events runs about
+        # 35 us longer on the 262k sphere, the side-stream schedule around
+        # them disturbed; kept off the other nine tenths); graph mode times
+        # them in an equal number of eager steps right after it.
+        n_ev = max(1, args.steps // 10)
+        # (a session of the same size before the timed region: the library
+        # keeps its events, so the one started inside the loop creates none)
+        n_rec = launches * (n_ev if not args.graph else args.steps) + 16
+        ops.profile_begin([dominant], n_rec)
+        ops.profile_end()
         torch.cuda.synchronize()
         ts = time.perf_counter()
         for i in range(args.steps):
             if not args.graph and i == args.steps - n_ev:
-                ops.profile_begin([dominant], launches * n_ev + 16)
+                ops.profile_begin([dominant], n_rec)
             phi = ops.matvec(qd, stream=st)
         torch.cuda.synchronize()
         te = time.perf_counter()
         eager_ms = None
         if args.graph:
-            ops.profile_begin([dominant], launches * args.steps + 16)
+            ops.profile_begin([dominant], n_rec)
             te0 = time.perf_counter()
             for _ in range(args.steps):
                 ops.matvec(qd, stream=st)

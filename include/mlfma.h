@@ -406,7 +406,11 @@ enum mlfma_kernel_id {
  * Diagnostics: time kernel launches of this handle with HIP events recorded
  * on the launch stream.  Every launch whose id bit is set in kernel_mask is
  * bracketed by an event pair, for at most max_launches launches (the events
- * are created here).  mlfma_profile_end waits for the events, writes the
+ * are created here, or taken from the handle's pool: the events of a
+ * session of up to 4096 launches are kept for the next one, so that a
+ * session started inside a timed loop after one of the same size creates
+ * none; the handle's destruction frees them).  mlfma_profile_end waits for
+ * the events, writes the
  * summed milliseconds and launch counts per id into ms[MLFMA_K_COUNT] and
  * launches[MLFMA_K_COUNT], and stops recording.  With MLFMA_PROFILE_SERIAL
  * set in kernel_mask, calls made while recording run every kernel on the

@@ -146,12 +146,17 @@ struct mlfma_ops_s {
     };
     std::vector<GraphEntry> graphs;
     uint64_t graph_clock = 0;
-    // launch timing (diagnostics)
+    // launch timing (diagnostics).  prof_ev is a pool: a session uses its
+    // first 2 prof_cap events; up to kProfPoolKeep of them outlive the
+    // session, so that a session of the same size started inside a timed
+    // loop creates no events there
     uint32_t prof_mask = 0;
     int64_t prof_cap = 0, prof_used = 0;
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_id;
 };
+
+constexpr size_t kProfPoolKeep = 8192;
 
 #define CK(x)                                                   \
     do {                                                        \
@@ -207,10 +212,13 @@ void prof_stop(mlfma_ops_s *o, hipStream_t s, int mode)
     ++o->prof_used;
 }
 
-void prof_release(mlfma_ops_s *o)
+// End a session; keep at most `keep` pooled events (0: destroy them all)
+void prof_release(mlfma_ops_s *o, size_t keep = 0)
 {
-    for (hipEvent_t e : o->prof_ev) (void)hipEventDestroy(e);
-    o->prof_ev.clear();
+    if (o->prof_ev.size() > keep) {
+        for (hipEvent_t e : o->prof_ev) (void)hipEventDestroy(e);
+        o->prof_ev.clear();
+    }
     o->prof_id.clear();
     o->prof_mask = 0;
     o->prof_cap = o->prof_used = 0;
@@ -1873,18 +1881,21 @@ int mlfma_profile_begin(mlfma_ops_t o, uint32_t kernel_mask, int64_t max_launche
     if (!o) return fail(MLFMA_EINVAL, "profile_begin: ops is NULL");
     if (max_launches < 0 || max_launches > (1 << 20))
         return fail(MLFMA_EINVAL, "profile_begin: max_launches outside 0..2^20");
-    prof_release(o);
+    prof_release(o, kProfPoolKeep);
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess) return fail(MLFMA_EDEVICE, "hipGetDevice failed");
     (void)hipSetDevice(o->device);
-    o->prof_ev.resize(2 * max_launches);
     int rc = MLFMA_OK;
-    for (int64_t i = 0; i < 2 * max_launches; ++i)
-        if (hipEventCreate(&o->prof_ev[i]) != hipSuccess) {
-            o->prof_ev.resize(i);
+    // grow the pool (timing only: no system-scope fence at their records,
+    // which would write back caches in the middle of the timed work)
+    while ((int64_t)o->prof_ev.size() < 2 * max_launches) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             rc = fail(MLFMA_EDEVICE, "profile_begin: hipEventCreate failed");
             break;
         }
+        o->prof_ev.push_back(e);
+    }
     (void)hipSetDevice(cur);
     if (rc) {
         prof_release(o);
@@ -1915,7 +1926,7 @@ int mlfma_profile_end(mlfma_ops_t o, double *ms, int64_t *launches)
         ms[o->prof_id[u]] += t;
         launches[o->prof_id[u]] += 1;
     }
-    prof_release(o);
+    prof_release(o, kProfPoolKeep);
     return rc;
 }
 
