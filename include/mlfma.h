@@ -71,7 +71,10 @@ enum mlfma_flags {
     MLFMA_BF16X3_INTERP = 1, /* interpolation GEMMs in BF16 split precision
                                 (hi*hi + hi*lo + lo*hi, FP32 accumulation)  */
     MLFMA_NO_AUTOTUNE = 2,   /* skip the kernel-variant timing at precompute
-                                (variants differ only in summation order)   */
+                                (variants differ only in summation order;
+                                the timing takes each form alone, then the
+                                close ones again inside the concurrent
+                                schedule, about 1 s for 262k points)        */
     MLFMA_USE_GRAPH = 4,     /* capture each distinct call (buffers, nrhs,
                                 dtype, parts, stream) into a HIP graph once
                                 and replay it afterwards; calls on the null

@@ -55,6 +55,7 @@ struct DevLevel {
                                      // the slice-major sweep, 5 = 3 record-balanced, 6 = 5 on
                                      // 32-sample slices, 7 = 5 on antipodal slices, 8 = 5 on
                                      // octant slices, 9 = 3 on the matrix cores (several RHS)
+    float m2l_alone[10] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // autotuner, ms per form
     int32_t *rec_start = nullptr, *rec_src = nullptr;  // records of the parents (level l-1)
     int32_t *rec_off = nullptr;      // [records][8] LDS byte offsets of the operators
     // antipodal slices (one-RHS variant 7): operators of one offset of each
@@ -81,6 +82,8 @@ struct DevLevel {
     // level pair (this level = parent): 0 three passes through HBM, 1 + k
     // one pass in work split k, 4 the fused pair kernel
     int interp_variant = 0, anterp_variant = 0;
+    // autotuner: ms alone of each of those variants (negative: not timed)
+    float interp_alone[5] = {-1, -1, -1, -1, -1}, anterp_alone[5] = {-1, -1, -1, -1, -1};
     bool onepass_ok = false;         // the one-pass kernels fit in LDS
     // fused pair kernel: parent groups (first, one past last) and operator
     // fragment tables of each direction
@@ -481,6 +484,7 @@ int autotune(mlfma_ops_s *o)
                 rc = fail(MLFMA_EDEVICE, "autotune: M2L variant %d failed", v);
                 break;
             }
+            o->lev[l].m2l_alone[v] = t;
             if (t < best) {
                 best = t;
                 bestv = v;
@@ -502,6 +506,8 @@ int autotune(mlfma_ops_s *o)
             break;
         }
         P.interp_variant = P.anterp_variant = 0;
+        P.interp_alone[0] = bi;
+        P.anterp_alone[0] = ba;
         for (int dn = 0; dn < 2 && rc == MLFMA_OK; ++dn) {
             if (!P.pair_ok[dn]) continue;
             const float tp = time_best(s, e0, e1, [&] { return launch_pair(o, l, R, s, dn); });
@@ -509,6 +515,7 @@ int autotune(mlfma_ops_s *o)
                 rc = fail(MLFMA_EDEVICE, "autotune: pair kernel failed on level %d", l);
                 break;
             }
+            (dn ? P.anterp_alone : P.interp_alone)[kPairVariant] = tp;
             float &best = dn ? ba : bi;
             if (tp < best) {
                 best = tp;
@@ -524,6 +531,8 @@ int autotune(mlfma_ops_s *o)
                 rc = fail(MLFMA_EDEVICE, "autotune: one-pass variant %d failed on level %d", k, l);
                 break;
             }
+            P.interp_alone[1 + k] = tf;
+            P.anterp_alone[1 + k] = af;
             if (tf < bi) {
                 bi = tf;
                 P.interp_variant = 1 + k;
@@ -662,63 +671,125 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
     return MLFMA_OK;
 }
 
-// Pick where the concurrent schedule forks the near field: time the core
-// (near + far field, max_rhs right-hand sides) for each fork point on a
-// scratch stream.
+// Times the core (near + far field, max_rhs right-hand sides) on a scratch
+// stream, as the concurrent schedule runs it, for the schedule tuners.
+struct CoreTimer {
+    mlfma_ops_s *o;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int reps = 3;
+    explicit CoreTimer(mlfma_ops_s *o_) : o(o_) {}
+    ~CoreTimer()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+    }
+    int init()
+    {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return fail(MLFMA_EDEVICE, "schedule tuning: stream or event creation failed");
+        // repetitions per timing: about 10 ms of matvecs (3 to 20), so that
+        // short matvecs are timed above the run-to-run noise
+        float t3 = 0.f;
+        if (int r = time(&t3)) return r;  // three cores
+        reps = std::max(3, std::min(20, (int)(30.f / std::max(t3, 1e-3f))));
+        return MLFMA_OK;
+    }
+    // ms for `reps` cores after one untimed core
+    int time(float *ms)
+    {
+        const int R = o->max_rhs;
+        if (int r = run_core(o, R, 0, MLFMA_NEAR | MLFMA_FAR, s)) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(MLFMA_EDEVICE, "schedule tuning: event");
+        for (int rep = 0; rep < reps; ++rep)
+            if (int r = run_core(o, R, 0, MLFMA_NEAR | MLFMA_FAR, s)) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return fail(MLFMA_EDEVICE, "schedule tuning: timing failed");
+        return MLFMA_OK;
+    }
+};
+
+// Pick where the concurrent schedule forks the near field and the share of
+// the CUs the side-stream M2L may hold: time the core for each pair.
 int tune_schedule(mlfma_ops_s *o)
 {
     if (!o->side[0] || o->n_lev < 3) return MLFMA_OK;
-    hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
-        return fail(MLFMA_EDEVICE, "tune_schedule: stream");
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    CoreTimer tm(o);
+    if (int r = tm.init()) return r;
     float best = 1e30f;
     int best_fork = 0, best_share = 6;
-    int rc = MLFMA_OK;
-    // repetitions per configuration: about 10 ms of matvecs (3 to 20), so
-    // that short matvecs are timed above the run-to-run noise
-    int reps = 3;
-    {
-        float t1 = 0.f;
-        rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
-        if (rc == MLFMA_OK && hipEventRecord(e0, s) == hipSuccess) {
-            rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
-            if (rc == MLFMA_OK && hipEventRecord(e1, s) == hipSuccess &&
-                hipEventSynchronize(e1) == hipSuccess &&
-                hipEventElapsedTime(&t1, e0, e1) == hipSuccess && t1 > 0.f)
-                reps = std::max(3, std::min(20, (int)(10.f / t1)));
-        }
-    }
     // M2L shares of 4/8 .. 8/8 of the CUs (8: uncapped) x the three fork
     // points of the near field
     constexpr int kShares[4] = {8, 7, 6, 4};
-    for (int cfg = 0; cfg < 12 && rc == MLFMA_OK; ++cfg) {
-        const int mode = cfg % 3, share = kShares[cfg / 3];
-        o->near_fork = mode;
-        o->m2l_share8 = share;
-        rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
+    for (int cfg = 0; cfg < 12; ++cfg) {
+        o->near_fork = cfg % 3;
+        o->m2l_share8 = kShares[cfg / 3];
         float t = 0.f;
-        if (rc == MLFMA_OK && hipEventRecord(e0, s) == hipSuccess) {
-            for (int rep = 0; rep < reps && rc == MLFMA_OK; ++rep)
-                rc = run_core(o, o->max_rhs, 0, MLFMA_NEAR | MLFMA_FAR, s);
-            if (rc == MLFMA_OK && hipEventRecord(e1, s) == hipSuccess &&
-                hipEventSynchronize(e1) == hipSuccess &&
-                hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best) {
-                best = t;
-                best_fork = mode;
-                best_share = share;
-            }
+        if (int r = tm.time(&t)) return r;
+        if (t < best) {
+            best = t;
+            best_fork = o->near_fork;
+            best_share = o->m2l_share8;
         }
     }
     o->near_fork = best_fork;
     o->m2l_share8 = best_share;
-    (void)hipStreamSynchronize(s);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipStreamDestroy(s);
-    return rc;
+    return MLFMA_OK;
+}
+
+// Refine the autotuner's per-kernel picks inside the concurrent schedule.
+// Forms of one kernel whose times alone differ by a few percent need not
+// rank the same way in the concurrent step, where they differ in the CUs
+// and LDS they hold beside the upward chain and the near field (on the 262k
+// sphere, one RHS, the leaf-adjacent M2L levels: the record form 5 and the
+// octant form 8 within a few percent of each other alone, 2% apart in the
+// step).  For each M2L level and each direction of each level pair, the
+// variants within 25% of the fastest alone are timed in the whole core, in
+// two alternating rounds, best of the two; a change needs a gain of 0.3%.
+int refine_schedule(mlfma_ops_s *o)
+{
+    if (!o->side[0] || o->n_lev < 3) return MLFMA_OK;
+    CoreTimer tm(o);
+    if (int r = tm.init()) return r;
+    auto refine = [&](int &knob, const float *alone, int nv) -> int {
+        float fastest = 1e30f;
+        for (int v = 0; v < nv; ++v)
+            if (alone[v] >= 0.f) fastest = std::min(fastest, alone[v]);
+        int cand[10], nc = 0;
+        for (int v = 0; v < nv; ++v)
+            if (alone[v] >= 0.f && alone[v] <= 1.25f * fastest) cand[nc++] = v;
+        if (nc < 2) return MLFMA_OK;
+        const int cur = knob;
+        float t[10];
+        for (float &x : t) x = 1e30f;
+        for (int round = 0; round < 2; ++round)
+            for (int i = 0; i < nc; ++i) {
+                knob = cand[i];
+                float ms = 0.f;
+                if (int r = tm.time(&ms)) {
+                    knob = cur;
+                    return r;
+                }
+                t[cand[i]] = std::min(t[cand[i]], ms);
+            }
+        int best = cur;
+        for (int i = 0; i < nc; ++i)
+            if (t[cand[i]] < t[best]) best = cand[i];
+        knob = (t[cur] < 1e30f && t[best] >= 0.997f * t[cur]) ? cur : best;
+        return MLFMA_OK;
+    };
+    for (int l = o->n_lev; l >= 3; --l)
+        if (int r = refine(o->lev[l].m2l_variant, o->lev[l].m2l_alone, 10)) return r;
+    for (int l = o->n_lev - 1; l >= 3; --l) {
+        DevLevel &P = o->lev[l];
+        if (int r = refine(P.interp_variant, P.interp_alone, 5)) return r;
+        if (int r = refine(P.anterp_variant, P.anterp_alone, 5)) return r;
+    }
+    return MLFMA_OK;
 }
 
 // conj_in/conj_out: -1 = follow MLFMA_CONJ in parts
@@ -1339,8 +1410,13 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             for (int l = 3; l <= nl; ++l)
                 if (hipEventCreateWithFlags(&o->ev_S[l], kEvFlags) != hipSuccess)
                     return fail(MLFMA_EDEVICE, "precompute: event creation failed");
-            if (!(flags & MLFMA_NO_AUTOTUNE))
+            if (!(flags & MLFMA_NO_AUTOTUNE)) {
+                // the fork point and CU share, then the kernel forms inside
+                // that schedule, then the schedule again for those forms
                 if ((r = tune_schedule(o))) return r;
+                if ((r = refine_schedule(o))) return r;
+                if ((r = tune_schedule(o))) return r;
+            }
         }
         return MLFMA_OK;
     }();
