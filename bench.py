@@ -118,11 +118,12 @@ for _k in ("interp_s1", "interp_s2", "interp_s3", "anterp_s1", "anterp_s2", "ant
     KERNEL_SOURCE[_k] = "interp.hip"
 
 
-def recorded_traffic(kernel, workload, nrhs):
+def recorded_traffic(kernel, workload, nrhs, forms=None):
     """HBM bytes per launch of `kernel` on `workload`, from the committed
     rocprofv3 counter summary profiles/<kernel>_<workload>_hbm_traffic.txt
     (FETCH_SIZE and WRITE_SIZE runs, scaled by the copy-kernel factors), or
-    None when there is none or the kernel source changed since."""
+    None when there is none, the kernel source changed since, or the summary
+    names the per-level forms it was taken with and `forms` differs."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.txt" % (kernel, workload))
     src = KERNEL_SOURCE.get(kernel)
@@ -136,6 +137,8 @@ def recorded_traffic(kernel, workload, nrhs):
     with open(os.path.join(ROOT, "paper_2006_15367_amd", "csrc", src), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
     if kv.get("source_sha256") != digest or int(kv.get("nrhs", -1)) != nrhs:
+        return None
+    if "forms" in kv and forms is not None and json.loads(kv["forms"]) != list(forms):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -449,6 +452,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (spheroid, 64 RHS, volume cloud)")
+    ap.add_argument("--forms", default=None,
+                    help="JSON object of kernel forms to take instead of autotuning, as "
+                         "the bench line's \"forms\" prints them: per-level lists "
+                         "(index = level - 1, -1 = none) for m2l, interp and anterp, and "
+                         "p2p = [near-field fork point, M2L CU share in eighths]; used to "
+                         "collect hardware counters of the forms a timed run chose")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -468,7 +477,17 @@ def main():
     tree = G.Tree(xyz, W.LEAF_SIZE)
     t1 = time.perf_counter()
     ops = G.Operators(tree, W.K_WAVENUMBER, W.DIGITS, max_rhs=R, bf16x3=args.bf16x3,
-                      graph=args.graph, one_stream=args.one_stream)
+                      graph=args.graph, one_stream=args.one_stream,
+                      autotune=args.forms is None)
+    if args.forms is not None:
+        forms = json.loads(args.forms)
+        for kern in ("m2l", "interp", "anterp"):
+            for i, v in enumerate(forms.get(kern, [])):
+                if v >= 0:
+                    ops.set_variant(i + 1, v, kern)
+        if "p2p" in forms and not args.one_stream and min(forms["p2p"]) >= 0:
+            ops.set_variant(0, forms["p2p"][0], "p2p")
+            ops.set_variant(1, forms["p2p"][1], "p2p")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     tinfo = tree.info()
@@ -574,7 +593,8 @@ def main():
     alone = roofline(dominant, work[dominant], dom_alone[0] / args.steps, launches, args.bf16x3)
     rl["event_steps"] = ev_steps
     rl["alone"] = {k: alone[k] for k in ("achieved", "frac", "avg_launch_us", "ms_per_step")}
-    rl["traffic"] = recorded_traffic(dominant, args.workload, R)
+    rl["traffic"] = recorded_traffic(dominant, args.workload, R,
+                                     ops.variants("m2l") if dominant == "m2l" else None)
     phases, floor_ms = phase_rooflines(work, {k: v[0] for k, v in per_kernel.items()},
                                        args.bf16x3)
     if rl["traffic"] is not None:
@@ -603,6 +623,7 @@ def main():
         "m2l_cu_share_eighths": ops.variants("p2p")[1],
         "onepass_interp_per_level": ops.variants("interp"),
         "onepass_anterp_per_level": ops.variants("anterp"),
+        "forms": {k: ops.variants(k) for k in ("m2l", "interp", "anterp", "p2p")},
         "roofline": rl,
         "phases": phases,
         "whole_matvec": {"floor_ms": round(floor_ms, 5), "ms": round(ms_per_step, 4),

@@ -36,6 +36,11 @@ def test_recorded_traffic_follows_the_source(tmp_path, monkeypatch):
     assert bench.recorded_traffic("m2l", "sphere262k", 1) == 1234.0
     assert bench.recorded_traffic("m2l", "sphere262k", 64) is None  # other RHS count
     assert bench.recorded_traffic("m2l", "spheroid1m", 1) is None  # no profile
+    # a summary that names its per-level forms applies only to those forms
+    prof.write_text("traffic_bytes_per_launch = 1234\nnrhs = 1\nsource_sha256 = %s\n"
+                    "forms = [-1, -1, 8, 7, 7, 8, 7]\n" % digest)
+    assert bench.recorded_traffic("m2l", "sphere262k", 1, [-1, -1, 8, 7, 7, 8, 7]) == 1234.0
+    assert bench.recorded_traffic("m2l", "sphere262k", 1, [-1, -1, 8, 7, 7, 5, 5]) is None
     src.write_bytes(b"// kernel source, changed\n")
     assert bench.recorded_traffic("m2l", "sphere262k", 1) is None
 
