@@ -618,7 +618,8 @@ def main():
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernel_ms_one_step": {k: round(v[0], 4) for k, v in per_kernel.items()},
         "m2l_variant_per_level": ops.variants("m2l"),
-        "near_field_fork": {0: "downward pass", 1: "start", 2: "after C2M"}.get(
+        "near_field_fork": {0: "downward pass", 1: "start", 2: "after C2M",
+                            3: "after the first M2M", 4: "after the second M2M"}.get(
             ops.variants("p2p")[0], "one stream"),
         "m2l_cu_share_eighths": ops.variants("p2p")[1],
         "onepass_interp_per_level": ops.variants("interp"),

@@ -452,11 +452,13 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * FP32 or BF16x3).
  * kernel = MLFMA_K_P2P (the concurrent schedule; two entries): out[0]
  * where it forks the near field, 1 at the start of the matvec, 2 after C2M,
- * 0 at the start of the downward pass; out[1] the eighths of the CUs the
- * M2L workgroups of levels above 3 may hold (4, 6, 7 or 8 from the precompute
- * timing); both -1 when every kernel runs on the caller's stream.
- * mlfma_ops_set_variant with this kernel sets the fork point (level != 1,
- * variant 0..2) or the M2L share (level 1, variant 1..8).
+ * 3 or 4 after the first or second M2M of the upward pass (trees of at least
+ * 4 or 5 levels), 0 at the start of the downward pass; out[1] the eighths of
+ * the CUs the M2L workgroups of levels above 3 may hold (4, 6, 7 or 8 from
+ * the precompute timing); both -1 when every kernel runs on the caller's
+ * stream.  mlfma_ops_set_variant with this kernel sets the fork point
+ * (level != 1, variant 0..4 as the tree allows) or the M2L share (level 1,
+ * variant 1..8).
  */
 int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
 /* Diagnostics: force a variant of `kernel` on `level` (3..n_levels; for the

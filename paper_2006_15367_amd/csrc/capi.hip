@@ -121,7 +121,8 @@ struct mlfma_ops_s {
     // the events that fork and join them
     hipStream_t side[2] = {nullptr, nullptr};
     // concurrent: where the near field forks: 0 start of the downward pass,
-    // 1 start of the matvec, 2 after C2M
+    // 1 start of the matvec, 2 after C2M, 3 / 4 after the first / second M2M
+    // of the upward pass
     int near_fork = 0;
     // concurrent: eighths of the CUs the M2L workgroups of levels > 3 may
     // hold (timed at precompute with the fork point)
@@ -584,8 +585,11 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
         return MLFMA_OK;
     };
     LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
-    if (fork == 2)
-        if (int r = near()) return r;
+    bool near_done = false;
+    if (fork == 2) {
+        if (int r = near(nullptr)) return r;
+        near_done = true;
+    }
     if (int r = m2l_level(nl)) return r;
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
@@ -601,12 +605,20 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
                               P.shift, P.S, s));
         }
         if (int r = m2l_level(l)) return r;
+        // fork points 3 and 4: after the first or second M2M of the upward
+        // pass (C2M and the finest M2Ms then run without the near field);
+        // the near-field stream waits on the event the M2L fork of this
+        // level recorded at the same point (one marker fewer)
+        if (!near_done && ((fork == 3 && l == nl - 1) || (fork == 4 && l == nl - 2))) {
+            if (int r = near(conc && l > 3 ? o->ev_S[l] : nullptr)) return r;
+            near_done = true;
+        }
     }
     // the near field forked here fills the device during the downward
     // pass, whose small kernels leave most CUs idle (forked at the start,
     // it takes CUs from C2M and the upward chain)
-    if (fork == 0)
-        if (int r = near()) return r;
+    if (fork == 0 || (fork >= 3 && !near_done))
+        if (int r = near(nullptr)) return r;
     if (conc) {
         CK(hipEventRecord(o->ev_m2l, sm));
         CK(hipStreamWaitEvent(s, o->ev_m2l, 0));
@@ -633,7 +645,8 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
 // The near field and the far field from the gathered charges o->qs up to
 // the leaf locals and o->near.  Concurrent schedule (side streams present,
 // not disabled): the near field runs on side[0], forked at the start
-// (o->near_fork 1), after C2M (2) or at the start of the downward pass (0),
+// (o->near_fork 1), after C2M (2), after the first or second M2M (3, 4) or
+// at the start of the downward pass (0),
 // and joined on `s` at the end; the M2L of each level but the last (level
 // 3) runs on side[1].
 int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
@@ -642,10 +655,15 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
     const int64_t nnear = o->n * R * (field ? 3 : 1);
     const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM) &&
                       !(o->prof_mask & MLFMA_PROFILE_SERIAL);
-    auto near = [&]() -> int {
+    // `after`: an event already recorded on s at the fork point, or null
+    // to record one
+    auto near = [&](hipEvent_t after) -> int {
         if (conc) {
-            CK(hipEventRecord(o->ev_fork, s));
-            CK(hipStreamWaitEvent(o->side[0], o->ev_fork, 0));
+            if (!after) {
+                CK(hipEventRecord(o->ev_fork, s));
+                after = o->ev_fork;
+            }
+            CK(hipStreamWaitEvent(o->side[0], after, 0));
         }
         hipStream_t s0 = s;
         hipStream_t s = conc ? o->side[0] : s0;
@@ -659,10 +677,10 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
         if (conc) CK(hipEventRecord(o->ev_near, s));
         return MLFMA_OK;
     };
-    auto none = []() -> int { return MLFMA_OK; };
+    auto none = [](hipEvent_t) -> int { return MLFMA_OK; };
     const bool early = !conc || o->near_fork == 1;
     if (early)
-        if (int r = near()) return r;
+        if (int r = near(nullptr)) return r;
     if (far) {
         const int r2 = early ? run_far(o, R, s, conc, none) : run_far(o, R, s, conc, near);
         if (r2) return r2;
@@ -722,20 +740,27 @@ int tune_schedule(mlfma_ops_s *o)
     if (int r = tm.init()) return r;
     float best = 1e30f;
     int best_fork = 0, best_share = 6;
-    // M2L shares of 4/8 .. 8/8 of the CUs (8: uncapped) x the three fork
-    // points of the near field
+    // M2L shares of 4/8 .. 8/8 of the CUs (8: uncapped) x the fork points
+    // of the near field (3 and 4 where the upward pass has that many M2Ms)
+    // (two alternating rounds, best of the two per configuration)
     constexpr int kShares[4] = {8, 7, 6, 4};
-    for (int cfg = 0; cfg < 12; ++cfg) {
-        o->near_fork = cfg % 3;
-        o->m2l_share8 = kShares[cfg / 3];
-        float t = 0.f;
-        if (int r = tm.time(&t)) return r;
-        if (t < best) {
-            best = t;
-            best_fork = o->near_fork;
-            best_share = o->m2l_share8;
+    const int nfork = std::min(5, 3 + std::max(0, o->n_lev - 3));
+    float t[20];
+    for (float &x : t) x = 1e30f;
+    for (int round = 0; round < 2; ++round)
+        for (int cfg = 0; cfg < 4 * nfork; ++cfg) {
+            o->near_fork = cfg % nfork;
+            o->m2l_share8 = kShares[cfg / nfork];
+            float ms = 0.f;
+            if (int r = tm.time(&ms)) return r;
+            t[cfg] = std::min(t[cfg], ms);
         }
-    }
+    for (int cfg = 0; cfg < 4 * nfork; ++cfg)
+        if (t[cfg] < best) {
+            best = t[cfg];
+            best_fork = cfg % nfork;
+            best_share = kShares[cfg / nfork];
+        }
     o->near_fork = best_fork;
     o->m2l_share8 = best_share;
     return MLFMA_OK;
@@ -1942,7 +1967,9 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
             if (variant < 1 || variant > 8) return fail(MLFMA_EINVAL, "ops_set_variant: bad M2L share %d", variant);
             o->m2l_share8 = variant;
         } else {
-            if (variant < 0 || variant > 2) return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
+            // fork points 3 and 4 need that many M2Ms in the upward pass
+            if (variant < 0 || variant > 2 + std::min(2, std::max(0, o->n_lev - 3)))
+                return fail(MLFMA_EINVAL, "ops_set_variant: bad variant %d", variant);
             o->near_fork = variant;
         }
     } else {

@@ -366,7 +366,8 @@ class Operators:
     def variants(self, kernel="m2l"):
         """Per-level kernel variant chosen by the autotuner (-1: no kernel).
         kernel="p2p": the concurrent schedule, [where it forks the near field
-        (1 at the start, 2 after C2M, 0 at the downward pass), eighths of the
+        (1 at the start, 2 after C2M, 3 / 4 after the first / second M2M, 0 at
+        the downward pass), eighths of the
         CUs the M2L workgroups of levels > 3 may hold]; [-1, -1] on one
         stream."""
         nl = self.tree.info()["n_levels"]

@@ -354,11 +354,13 @@ def test_concurrent_schedule_equals_one_stream(c1):
     Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
     Qd = torch.from_numpy(Q).cuda()
     tuned, share = ops.variants("p2p")
-    assert tuned in (0, 1, 2) and share in (4, 6, 7, 8) and ops1.variants("p2p") == [-1, -1]
+    # (four levels: one M2M, so fork point 4 does not exist)
+    assert tuned in (0, 1, 2, 3) and share in (4, 6, 7, 8) and ops1.variants("p2p") == [-1, -1]
     try:
-        # near field forked at the downward pass / start / after C2M; M2L
-        # of levels > 3 on half, three quarters or all of the CUs
-        for fork, sh in ((0, 6), (1, 6), (2, 6), (1, 4), (2, 8)):
+        # near field forked at the downward pass / start / after C2M /
+        # after the M2M; M2L of levels > 3 on half, three quarters or all
+        # of the CUs
+        for fork, sh in ((0, 6), (1, 6), (2, 6), (1, 4), (2, 8), (3, 6), (3, 8)):
             ops.set_variant(0, fork, kernel="p2p")
             ops.set_variant(1, sh, kernel="p2p")
             for rep in range(3):
@@ -413,7 +415,7 @@ def test_variant_and_schedule_limits(c1):
     before = (ops.variants("m2l"), ops.variants("p2p"))
     bad = [
         (3, 10, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
-        (0, 3, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
+        (0, 4, "p2p"), (0, 5, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
         (nl, 0, "interp"),
     ]
     for level, variant, kernel in bad:
