@@ -127,6 +127,10 @@ struct mlfma_ops_s {
     // concurrent: eighths of the CUs the M2L workgroups of levels > 3 may
     // hold (timed at precompute with the fork point)
     int m2l_share8 = 6;
+    // concurrent: 1 = the leaf level's M2L runs after the coarser levels'
+    // on its stream, during the downward pass (it is first needed by the
+    // last L2L), instead of beside the upward pass
+    int leaf_late = 0;
     // GMRES workspace: Krylov basis [(gm_cap + 1) x n], work vector,
     // dot-product partials, coefficient vector (allocated on first solve)
     int gm_cap = 0;
@@ -135,7 +139,7 @@ struct mlfma_ops_s {
     int64_t planned_bytes = 0;       // device bytes of the precompute
     int64_t operator_bytes = 0;      // of which translation operators
     bool sampled = false;            // MLFMA_SAMPLED_OPERATORS
-    hipEvent_t ev_fork = nullptr, ev_near = nullptr, ev_m2l = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_near = nullptr, ev_m2l = nullptr, ev_leaf = nullptr;
     std::vector<hipEvent_t> ev_S;  // per level: multipoles ready
     // captured graphs of previous calls (MLFMA_USE_GRAPH)
     struct GraphEntry {
@@ -274,7 +278,7 @@ void free_ops(mlfma_ops_s *o)
             (void)hipSetDevice(o->device);
             for (hipStream_t &st : o->side)
                 if (st) (void)hipStreamDestroy(st);
-            for (hipEvent_t e : {o->ev_fork, o->ev_near, o->ev_m2l})
+            for (hipEvent_t e : {o->ev_fork, o->ev_near, o->ev_m2l, o->ev_leaf})
                 if (e) (void)hipEventDestroy(e);
             for (hipEvent_t e : o->ev_S)
                 if (e) (void)hipEventDestroy(e);
@@ -564,12 +568,14 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     const float kw = (float)o->k;
     const bool b3 = (o->flags & MLFMA_BF16X3_INTERP) != 0;
     hipStream_t sm = conc ? o->side[1] : s;
+    bool side_used = false;  // an M2L ran on sm
     auto m2l_level = [&](int l) -> int {
         // level 3, the last, stays on the caller's stream: the downward
         // pass waits for it anyway, and a fork and join around it cost
         // more than the overlap gains
         const bool side = conc && l > 3;
         if (side) {
+            side_used = true;
             CK(hipEventRecord(o->ev_S[l], s));
             CK(hipStreamWaitEvent(sm, o->ev_S[l], 0));
         }
@@ -590,7 +596,13 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
         if (int r = near(nullptr)) return r;
         near_done = true;
     }
-    if (int r = m2l_level(nl)) return r;
+    // leaf M2L late: its spectra are ready here (event), its launch waits
+    // until the coarser levels' M2L are enqueued on the M2L stream
+    const bool leaf_late = conc && o->leaf_late && nl > 3;
+    if (leaf_late)
+        CK(hipEventRecord(o->ev_S[nl], s));
+    else if (int r = m2l_level(nl))
+        return r;
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
@@ -619,13 +631,28 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     // it takes CUs from C2M and the upward chain)
     if (fork == 0 || (fork >= 3 && !near_done))
         if (int r = near(nullptr)) return r;
-    if (conc) {
+    // join the M2L stream: an event recorded on it is part of a captured
+    // graph only once it waited on an event of the capture, so where no
+    // coarser level ran on it (four levels, leaf late) it first takes the
+    // leaf M2L's wait, and where no M2L ran on it at all there is no join
+    if (conc && leaf_late && !side_used) CK(hipStreamWaitEvent(sm, o->ev_S[nl], 0));
+    if (conc && (side_used || leaf_late)) {
         CK(hipEventRecord(o->ev_m2l, sm));
+        if (leaf_late) {
+            if (side_used) CK(hipStreamWaitEvent(sm, o->ev_S[nl], 0));
+            hipStream_t s = sm;  // (LAUNCH times on the launch stream)
+            const int cap = dev::cu_count() * o->m2l_share8 / 8;
+            LAUNCH(MLFMA_K_M2L, launch_m2l(o, nl, leaf.m2l_variant, R, s, cap));
+            CK(hipEventRecord(o->ev_leaf, s));
+        }
         CK(hipStreamWaitEvent(s, o->ev_m2l, 0));
     }
     for (int l = 3; l < nl; ++l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
+        // the last L2L adds into the leaf locals the leaf M2L wrote
+        if (leaf_late && l == nl - 1)
+            CK(hipStreamWaitEvent(s, o->ev_leaf, 0));
         if (P.anterp_variant == kPairVariant) {
             LAUNCH(MLFMA_K_ANTERP, launch_pair(o, l, R, s, 1));
             continue;
@@ -696,6 +723,7 @@ struct CoreTimer {
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int reps = 3;
+    bool warm = true;  // one untimed core before each timing
     explicit CoreTimer(mlfma_ops_s *o_) : o(o_) {}
     ~CoreTimer()
     {
@@ -709,18 +737,22 @@ struct CoreTimer {
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return fail(MLFMA_EDEVICE, "schedule tuning: stream or event creation failed");
-        // repetitions per timing: about 10 ms of matvecs (3 to 20), so that
-        // short matvecs are timed above the run-to-run noise
+        // repetitions per timing: about 10 ms of cores (1 to 20), so that
+        // short cores are timed above the run-to-run noise and long ones
+        // (many RHS, 20-60 ms a core) do not make precompute slow; the
+        // untimed core before each timing only for cores under 2 ms
         float t3 = 0.f;
         if (int r = time(&t3)) return r;  // three cores
-        reps = std::max(3, std::min(20, (int)(30.f / std::max(t3, 1e-3f))));
+        reps = std::max(1, std::min(20, (int)(30.f / std::max(t3, 1e-3f))));
+        warm = t3 < 6.f;
         return MLFMA_OK;
     }
     // ms for `reps` cores after one untimed core
     int time(float *ms)
     {
         const int R = o->max_rhs;
-        if (int r = run_core(o, R, 0, MLFMA_NEAR | MLFMA_FAR, s)) return r;
+        if (warm)
+            if (int r = run_core(o, R, 0, MLFMA_NEAR | MLFMA_FAR, s)) return r;
         if (hipEventRecord(e0, s) != hipSuccess) return fail(MLFMA_EDEVICE, "schedule tuning: event");
         for (int rep = 0; rep < reps; ++rep)
             if (int r = run_core(o, R, 0, MLFMA_NEAR | MLFMA_FAR, s)) return r;
@@ -739,30 +771,35 @@ int tune_schedule(mlfma_ops_s *o)
     CoreTimer tm(o);
     if (int r = tm.init()) return r;
     float best = 1e30f;
-    int best_fork = 0, best_share = 6;
+    int best_cfg = 0;
     // M2L shares of 4/8 .. 8/8 of the CUs (8: uncapped) x the fork points
     // of the near field (3 and 4 where the upward pass has that many M2Ms)
-    // (two alternating rounds, best of the two per configuration)
+    // x the leaf M2L early or late (trees of more than 3 levels); two
+    // alternating rounds, best of the two per configuration
     constexpr int kShares[4] = {8, 7, 6, 4};
     const int nfork = std::min(5, 3 + std::max(0, o->n_lev - 3));
-    float t[20];
+    const int nlate = o->n_lev > 3 ? 2 : 1;
+    const int ncfg = 4 * nfork * nlate;
+    auto apply = [&](int cfg) {
+        o->near_fork = cfg % nfork;
+        o->m2l_share8 = kShares[cfg / nfork % 4];
+        o->leaf_late = cfg / (4 * nfork);
+    };
+    float t[40];
     for (float &x : t) x = 1e30f;
     for (int round = 0; round < 2; ++round)
-        for (int cfg = 0; cfg < 4 * nfork; ++cfg) {
-            o->near_fork = cfg % nfork;
-            o->m2l_share8 = kShares[cfg / nfork];
+        for (int cfg = 0; cfg < ncfg; ++cfg) {
+            apply(cfg);
             float ms = 0.f;
             if (int r = tm.time(&ms)) return r;
             t[cfg] = std::min(t[cfg], ms);
         }
-    for (int cfg = 0; cfg < 4 * nfork; ++cfg)
+    for (int cfg = 0; cfg < ncfg; ++cfg)
         if (t[cfg] < best) {
             best = t[cfg];
-            best_fork = cfg % nfork;
-            best_share = kShares[cfg / nfork];
+            best_cfg = cfg;
         }
-    o->near_fork = best_fork;
-    o->m2l_share8 = best_share;
+    apply(best_cfg);
     return MLFMA_OK;
 }
 
@@ -814,6 +851,83 @@ int refine_schedule(mlfma_ops_s *o)
         if (int r = refine(P.interp_variant, P.interp_alone, 5)) return r;
         if (int r = refine(P.anterp_variant, P.anterp_alone, 5)) return r;
     }
+    return MLFMA_OK;
+}
+
+// Schedule and kernel forms of the concurrent step: the schedule (fork
+// point, CU share, leaf M2L order), then the forms inside it, then the
+// schedule again for those forms, from two starting points: the forms
+// fastest alone, and the octant M2L form (the least LDS per workgroup, so
+// the most room for the kernels beside it) on every level but the leaf,
+// with the record form on the leaf.
+// The search is greedy and the step's optimum is joint: on the 262k sphere
+// the second start reaches octant forms on levels 3..6 with the leaf's
+// record form run late on half the CUs (0.557 ms), which no single change
+// from the first start's result (0.571 ms) improves on.  The better of the
+// two results, timed again in alternation, is kept.
+int tune_concurrent(mlfma_ops_s *o)
+{
+    const int nl = o->n_lev;
+    struct Pick {
+        int fork, share, late;
+        std::vector<int> m2l, interp, anterp;
+    };
+    auto save = [&]() {
+        Pick p{o->near_fork, o->m2l_share8, o->leaf_late, {}, {}, {}};
+        for (int l = 3; l <= nl; ++l) {
+            p.m2l.push_back(o->lev[l].m2l_variant);
+            p.interp.push_back(o->lev[l].interp_variant);
+            p.anterp.push_back(o->lev[l].anterp_variant);
+        }
+        return p;
+    };
+    auto restore = [&](const Pick &p) {
+        o->near_fork = p.fork;
+        o->m2l_share8 = p.share;
+        o->leaf_late = p.late;
+        for (int l = 3; l <= nl; ++l) {
+            o->lev[l].m2l_variant = p.m2l[l - 3];
+            o->lev[l].interp_variant = p.interp[l - 3];
+            o->lev[l].anterp_variant = p.anterp[l - 3];
+        }
+    };
+    auto search = [&]() -> int {
+        if (int r = tune_schedule(o)) return r;
+        if (int r = refine_schedule(o)) return r;
+        return tune_schedule(o);
+    };
+    const Pick start = save();
+    if (int r = search()) return r;
+    const Pick first = save();
+    bool octant = false;
+    restore(start);
+    for (int l = 3; l < nl; ++l)
+        if (o->lev[l].m2l_alone[8] >= 0.f && o->lev[l].m2l_variant != 8) {
+            o->lev[l].m2l_variant = 8;
+            octant = true;
+        }
+    if (!octant) {
+        restore(first);
+        return MLFMA_OK;
+    }
+    // and the leaf on the record form 5 (one workgroup per CU, the form
+    // that leaves the most CUs whole to the kernels beside it when capped)
+    if (o->lev[nl].m2l_alone[5] >= 0.f) o->lev[nl].m2l_variant = 5;
+    if (int r = search()) return r;
+    const Pick second = save();
+    CoreTimer tm(o);
+    if (int r = tm.init()) return r;
+    float t1 = 1e30f, t2 = 1e30f;
+    for (int round = 0; round < 3; ++round) {
+        float ms = 0.f;
+        restore(first);
+        if (int r = tm.time(&ms)) return r;
+        t1 = std::min(t1, ms);
+        restore(second);
+        if (int r = tm.time(&ms)) return r;
+        t2 = std::min(t2, ms);
+    }
+    restore(t2 < t1 ? second : first);
     return MLFMA_OK;
 }
 
@@ -1429,18 +1543,14 @@ int mlfma_precompute_operators(mlfma_tree_t th, double k, int digits, int max_rh
             // of the 262k sphere took 0.589 ms, without it 0.583 ms)
             constexpr unsigned kEvFlags = hipEventDisableTiming | hipEventDisableSystemFence;
             o->ev_S.assign(nl + 1, nullptr);
-            for (hipEvent_t *e : {&o->ev_fork, &o->ev_near, &o->ev_m2l})
+            for (hipEvent_t *e : {&o->ev_fork, &o->ev_near, &o->ev_m2l, &o->ev_leaf})
                 if (hipEventCreateWithFlags(e, kEvFlags) != hipSuccess)
                     return fail(MLFMA_EDEVICE, "precompute: event creation failed");
             for (int l = 3; l <= nl; ++l)
                 if (hipEventCreateWithFlags(&o->ev_S[l], kEvFlags) != hipSuccess)
                     return fail(MLFMA_EDEVICE, "precompute: event creation failed");
             if (!(flags & MLFMA_NO_AUTOTUNE)) {
-                // the fork point and CU share, then the kernel forms inside
-                // that schedule, then the schedule again for those forms
-                if ((r = tune_schedule(o))) return r;
-                if ((r = refine_schedule(o))) return r;
-                if ((r = tune_schedule(o))) return r;
+                if ((r = tune_concurrent(o))) return r;
             }
         }
         return MLFMA_OK;
@@ -1929,6 +2039,7 @@ int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
     if (kernel == MLFMA_K_P2P) {
         if (max_entries >= 1) out[0] = o->side[0] ? o->near_fork : -1;
         if (max_entries >= 2) out[1] = o->side[0] ? o->m2l_share8 : -1;
+        if (max_entries >= 3) out[2] = o->side[0] ? o->leaf_late : -1;
         return MLFMA_OK;
     }
     return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
@@ -1966,6 +2077,9 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
         if (level == 1) {
             if (variant < 1 || variant > 8) return fail(MLFMA_EINVAL, "ops_set_variant: bad M2L share %d", variant);
             o->m2l_share8 = variant;
+        } else if (level == 2) {
+            if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad leaf M2L order %d", variant);
+            o->leaf_late = variant;
         } else {
             // fork points 3 and 4 need that many M2Ms in the upward pass
             if (variant < 0 || variant > 2 + std::min(2, std::max(0, o->n_lev - 3)))

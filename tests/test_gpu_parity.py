@@ -353,26 +353,31 @@ def test_concurrent_schedule_equals_one_stream(c1):
     n = c1["xyz"].shape[0]
     Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
     Qd = torch.from_numpy(Q).cuda()
-    tuned, share = ops.variants("p2p")
+    tuned, share, late = ops.variants("p2p")
     # (four levels: one M2M, so fork point 4 does not exist)
-    assert tuned in (0, 1, 2, 3) and share in (4, 6, 7, 8) and ops1.variants("p2p") == [-1, -1]
+    assert tuned in (0, 1, 2, 3) and share in (4, 6, 7, 8) and late in (0, 1)
+    assert ops1.variants("p2p") == [-1, -1, -1]
     try:
         # near field forked at the downward pass / start / after C2M /
         # after the M2M; M2L of levels > 3 on half, three quarters or all
-        # of the CUs
-        for fork, sh in ((0, 6), (1, 6), (2, 6), (1, 4), (2, 8), (3, 6), (3, 8)):
+        # of the CUs; the leaf M2L beside the upward pass or after the
+        # coarser levels' M2L
+        for fork, sh, lt in ((0, 6, 0), (1, 6, 0), (2, 6, 0), (1, 4, 0), (2, 8, 0),
+                             (3, 6, 0), (3, 8, 0), (1, 6, 1), (0, 8, 1), (3, 7, 1)):
             ops.set_variant(0, fork, kernel="p2p")
             ops.set_variant(1, sh, kernel="p2p")
+            ops.set_variant(2, lt, kernel="p2p")
             for rep in range(3):
                 a = _run(c1, ops.matvec, Qd)
                 b = _run(c1, ops1.matvec, Qd)
-                assert np.array_equal(a, b), (fork, sh, rep)
+                assert np.array_equal(a, b), (fork, sh, lt, rep)
             fa = _run(c1, ops.field, Qd[:, 0].contiguous())
             fb = _run(c1, ops1.field, Qd[:, 0].contiguous())
-            assert np.array_equal(fa, fb), (fork, sh)
+            assert np.array_equal(fa, fb), (fork, sh, lt)
     finally:
         ops.set_variant(0, tuned, kernel="p2p")
         ops.set_variant(1, share, kernel="p2p")
+        ops.set_variant(2, late, kernel="p2p")
 
 
 def test_graph_replays_match_eager(c1):
@@ -388,16 +393,21 @@ def test_graph_replays_match_eager(c1):
     st = torch.cuda.Stream()
     out = torch.empty_like(qd)
     rng = np.random.default_rng(61)
-    for rep in range(4):
-        with torch.cuda.stream(st):
-            phi = ops_g.matvec(qd, stream=st)
-        st.synchronize()
-        got = phi.cpu().numpy()
-        assert rel_l2(got, eager) < 1e-6, rep
-        # unrelated eager work between replays
-        x = torch.from_numpy(rng.standard_normal(4096).astype(np.complex64)).cuda()
-        c1["gops"].matvec(x)
-        torch.cuda.synchronize()
+    # both orders of the leaf M2L (beside the upward pass, or after the
+    # coarser levels during the downward pass: on this four-level tree the
+    # M2L stream then joins the capture through the leaf's own wait)
+    for lt in (0, 1, ops_g.variants("p2p")[2]):
+        ops_g.set_variant(2, lt, kernel="p2p")
+        for rep in range(4):
+            with torch.cuda.stream(st):
+                phi = ops_g.matvec(qd, stream=st)
+            st.synchronize()
+            got = phi.cpu().numpy()
+            assert rel_l2(got, eager) < 1e-6, (lt, rep)
+            # unrelated eager work between replays
+            x = torch.from_numpy(rng.standard_normal(4096).astype(np.complex64)).cuda()
+            c1["gops"].matvec(x)
+            torch.cuda.synchronize()
     # adjoint through the graph path too
     with torch.cuda.stream(st):
         psi = ops_g.adjoint(qd, stream=st)
@@ -416,6 +426,7 @@ def test_variant_and_schedule_limits(c1):
     bad = [
         (3, 10, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
         (0, 4, "p2p"), (0, 5, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
+        (2, 2, "p2p"), (2, -1, "p2p"),
         (nl, 0, "interp"),
     ]
     for level, variant, kernel in bad:

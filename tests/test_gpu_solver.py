@@ -87,7 +87,8 @@ def test_gmres_on_a_graph_handle_equals_eager(case):
         for l in range(3, nl + 1):
             if v[l - 1] >= 0:
                 gops.set_variant(l, v[l - 1], kernel=k)
-    gops.set_variant(0, ops.variants("p2p")[0], kernel="p2p")
+    for i, v in enumerate(ops.variants("p2p")):  # fork point, share, leaf order
+        gops.set_variant(i, v, kernel="p2p")
     st = torch.cuda.Stream()
     bd = torch.from_numpy(case["b"].astype(np.complex64)).cuda()
     with torch.cuda.stream(st):
