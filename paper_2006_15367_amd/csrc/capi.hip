@@ -596,13 +596,17 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
         if (int r = near(nullptr)) return r;
         near_done = true;
     }
-    // leaf M2L late: its spectra are ready here (event), its launch waits
-    // until the coarser levels' M2L are enqueued on the M2L stream
+    // leaf M2L late: it is enqueued on the M2L stream after the coarser
+    // levels' M2L, whose forks (recorded here on s after C2M and the M2Ms)
+    // already order it after C2M; only a four-level tree, whose one
+    // coarser level runs on s, needs an event of its own (a marker on s
+    // costs about 5 us of the critical path)
     const bool leaf_late = conc && o->leaf_late && nl > 3;
-    if (leaf_late)
+    const bool leaf_event = leaf_late && nl == 4;
+    if (leaf_event)
         CK(hipEventRecord(o->ev_S[nl], s));
-    else if (int r = m2l_level(nl))
-        return r;
+    else if (!leaf_late)
+        if (int r = m2l_level(nl)) return r;
     for (int l = nl - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l], &C = o->lev[l + 1];
         const int M = P.Mc;
@@ -635,11 +639,10 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     // graph only once it waited on an event of the capture, so where no
     // coarser level ran on it (four levels, leaf late) it first takes the
     // leaf M2L's wait, and where no M2L ran on it at all there is no join
-    if (conc && leaf_late && !side_used) CK(hipStreamWaitEvent(sm, o->ev_S[nl], 0));
+    if (leaf_event) CK(hipStreamWaitEvent(sm, o->ev_S[nl], 0));
     if (conc && (side_used || leaf_late)) {
         CK(hipEventRecord(o->ev_m2l, sm));
         if (leaf_late) {
-            if (side_used) CK(hipStreamWaitEvent(sm, o->ev_S[nl], 0));
             hipStream_t s = sm;  // (LAUNCH times on the launch stream)
             const int cap = dev::cu_count() * o->m2l_share8 / 8;
             LAUNCH(MLFMA_K_M2L, launch_m2l(o, nl, leaf.m2l_variant, R, s, cap));
