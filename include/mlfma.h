@@ -72,9 +72,10 @@ enum mlfma_flags {
                                 (hi*hi + hi*lo + lo*hi, FP32 accumulation)  */
     MLFMA_NO_AUTOTUNE = 2,   /* skip the kernel-variant timing at precompute
                                 (variants differ only in summation order;
-                                the timing takes each form alone, then the
-                                close ones again inside the concurrent
-                                schedule, about 1 s for 262k points)        */
+                                the timing takes each form alone, then
+                                searches the concurrent schedule with the
+                                close forms inside the whole step, about
+                                5 s for 262k points at one RHS)             */
     MLFMA_USE_GRAPH = 4,     /* capture each distinct call (buffers, nrhs,
                                 dtype, parts, stream) into a HIP graph once
                                 and replay it afterwards; calls on the null
