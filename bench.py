@@ -457,7 +457,7 @@ def main():
                          "the bench line's \"forms\" prints them: per-level lists "
                          "(index = level - 1, -1 = none) for m2l, interp and anterp, and "
                          "p2p = [near-field fork point, M2L CU share in eighths, leaf "
-                         "M2L late 0/1]; used to "
+                         "M2L late 0/1, near field in two halves 0/1]; used to "
                          "collect hardware counters of the forms a timed run chose")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
@@ -487,7 +487,8 @@ def main():
                 if v >= 0:
                     ops.set_variant(i + 1, v, kern)
         if "p2p" in forms and not args.one_stream and min(forms["p2p"]) >= 0:
-            # [fork point, M2L CU share, leaf M2L late] as levels 0, 1, 2
+            # [fork point, M2L CU share, leaf M2L late, near field halves]
+            # as levels 0, 1, 2, 3
             for i, v in enumerate(forms["p2p"]):
                 ops.set_variant(i, v, "p2p")
     torch.cuda.synchronize()
@@ -626,6 +627,7 @@ def main():
         "m2l_cu_share_eighths": ops.variants("p2p")[1],
         "leaf_m2l": {0: "beside the upward pass", 1: "during the downward pass"}.get(
             ops.variants("p2p")[2], "one stream"),
+        "near_field_halves": ops.variants("p2p")[3],
         "onepass_interp_per_level": ops.variants("interp"),
         "onepass_anterp_per_level": ops.variants("anterp"),
         "forms": {k: ops.variants(k) for k in ("m2l", "interp", "anterp", "p2p")},

@@ -451,18 +451,20 @@ int mlfma_profile_end(mlfma_ops_t ops, double *ms, int64_t *launches);
  * 8 -> 13, 2 for 13 -> 20; FP32 only), 4 the fused pair kernel (the maps,
  * shift and sibling sum or add in one launch; bands 8 -> 13 and 13 -> 20,
  * FP32 or BF16x3).
- * kernel = MLFMA_K_P2P (the concurrent schedule; three entries): out[0]
+ * kernel = MLFMA_K_P2P (the concurrent schedule; four entries): out[0]
  * where it forks the near field, 1 at the start of the matvec, 2 after C2M,
  * 3 or 4 after the first or second M2M of the upward pass (trees of at least
  * 4 or 5 levels), 0 at the start of the downward pass; out[1] the eighths of
  * the CUs the M2L workgroups of levels above 3 may hold (4, 6, 7 or 8 from
  * the precompute timing); out[2] 1 where the leaf level's M2L runs after the
  * coarser levels' M2L, during the downward pass (trees of more than 3
- * levels), 0 where it runs first, beside the upward pass; all -1 when every
- * kernel runs on the caller's stream.  mlfma_ops_set_variant with this
- * kernel sets the M2L share (level 1, variant 1..8), the leaf M2L order
- * (level 2, variant 0..1) or the fork point (any other level, variant 0..4
- * as the tree allows).
+ * levels), 0 where it runs first, beside the upward pass; out[3] 1 where
+ * the near field, forked after an M2M, runs in two halves of its work items,
+ * the second forked after the next M2M; all -1 when every kernel runs on the
+ * caller's stream.  mlfma_ops_set_variant with this kernel sets the M2L
+ * share (level 1, variant 1..8), the leaf M2L order (level 2, variant 0..1),
+ * the near-field split (level 3, variant 0..1) or the fork point (any other
+ * level, variant 0..4 as the tree allows).
  */
 int mlfma_ops_variants(mlfma_ops_t ops, int kernel, int32_t *out, int max_entries);
 /* Diagnostics: force a variant of `kernel` on `level` (3..n_levels; for the

@@ -131,6 +131,9 @@ struct mlfma_ops_s {
     // on its stream, during the downward pass (it is first needed by the
     // last L2L), instead of beside the upward pass
     int leaf_late = 0;
+    // concurrent, fork after an M2M: 1 = the near field in two halves of its
+    // work items, the second forked after the next M2M
+    int near_split = 0;
     // GMRES workspace: Krylov basis [(gm_cap + 1) x n], work vector,
     // dot-product partials, coefficient vector (allocated on first solve)
     int gm_cap = 0;
@@ -593,9 +596,11 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
     LAUNCH(MLFMA_K_C2M, dev::c2m(o->pts, o->pt_start, leaf.nbox, leaf.khat_w, leaf.K, kw, o->qs, R, leaf.S, s));
     bool near_done = false;
     if (fork == 2) {
-        if (int r = near(nullptr)) return r;
+        if (int r = near(nullptr, 0)) return r;
         near_done = true;
     }
+    const bool split = conc && o->near_split && fork >= 3;
+    bool split_pending = false;
     // leaf M2L late: it is enqueued on the M2L stream after the coarser
     // levels' M2L, whose forks (recorded here on s after C2M and the M2Ms)
     // already order it after C2M; only a four-level tree, whose one
@@ -626,15 +631,22 @@ int run_far(mlfma_ops_s *o, int R, hipStream_t s, bool conc, Near &&near)
         // the near-field stream waits on the event the M2L fork of this
         // level recorded at the same point (one marker fewer)
         if (!near_done && ((fork == 3 && l == nl - 1) || (fork == 4 && l == nl - 2))) {
-            if (int r = near(conc && l > 3 ? o->ev_S[l] : nullptr)) return r;
+            if (int r = near(conc && l > 3 ? o->ev_S[l] : nullptr, split ? 1 : 0)) return r;
             near_done = true;
+            split_pending = split;
+        } else if (split_pending) {
+            // the second half after the next M2M
+            if (int r = near(conc && l > 3 ? o->ev_S[l] : nullptr, 2)) return r;
+            split_pending = false;
         }
     }
+    if (split_pending)
+        if (int r = near(nullptr, 2)) return r;
     // the near field forked here fills the device during the downward
     // pass, whose small kernels leave most CUs idle (forked at the start,
     // it takes CUs from C2M and the upward chain)
     if (fork == 0 || (fork >= 3 && !near_done))
-        if (int r = near(nullptr)) return r;
+        if (int r = near(nullptr, 0)) return r;
     // join the M2L stream: an event recorded on it is part of a captured
     // graph only once it waited on an event of the capture, so where no
     // coarser level ran on it (four levels, leaf late) it first takes the
@@ -686,8 +698,10 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
     const bool conc = far && o->side[0] && !(o->flags & MLFMA_ONE_STREAM) &&
                       !(o->prof_mask & MLFMA_PROFILE_SERIAL);
     // `after`: an event already recorded on s at the fork point, or null
-    // to record one
-    auto near = [&](hipEvent_t after) -> int {
+    // to record one; `part`: 0 all work items, 1 / 2 the first / second
+    // half (the heavy items and half the others / the rest; the items
+    // write disjoint targets)
+    auto near = [&](hipEvent_t after, int part) -> int {
         if (conc) {
             if (!after) {
                 CK(hipEventRecord(o->ev_fork, s));
@@ -697,20 +711,32 @@ int run_core(mlfma_ops_s *o, int R, int field, uint32_t parts, hipStream_t s)
         }
         hipStream_t s0 = s;
         hipStream_t s = conc ? o->side[0] : s0;
-        if (parts & MLFMA_NEAR)
-            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items, o->n_p2p_items, o->n_p2p_heavy, o->pts,
+        if (parts & MLFMA_NEAR) {
+            int64_t i0 = 0, ni = o->n_p2p_items, nh = o->n_p2p_heavy;
+            if (part) {
+                const int64_t cut = o->n_p2p_heavy + (o->n_p2p_items - o->n_p2p_heavy) / 2;
+                if (part == 1) {
+                    ni = cut;
+                } else {
+                    i0 = cut;
+                    ni = o->n_p2p_items - cut;
+                    nh = 0;
+                }
+            }
+            LAUNCH(MLFMA_K_P2P, dev::p2p(o->p2p_items + i0, ni, nh, o->pts,
                                          o->pt_start, o->near_start, o->near_idx, o->leaf_coord,
                                          (float)o->tree->leaf, (float)o->k, o->qs, R, field,
                                          o->near, s));
-        else
+        } else if (part != 2) {
             LAUNCH(MLFMA_K_P2P, dev::zero(o->near, nnear, s));
+        }
         if (conc) CK(hipEventRecord(o->ev_near, s));
         return MLFMA_OK;
     };
-    auto none = [](hipEvent_t) -> int { return MLFMA_OK; };
+    auto none = [](hipEvent_t, int) -> int { return MLFMA_OK; };
     const bool early = !conc || o->near_fork == 1;
     if (early)
-        if (int r = near(nullptr)) return r;
+        if (int r = near(nullptr, 0)) return r;
     if (far) {
         const int r2 = early ? run_far(o, R, s, conc, none) : run_far(o, R, s, conc, near);
         if (r2) return r2;
@@ -820,13 +846,8 @@ int refine_schedule(mlfma_ops_s *o)
     if (!o->side[0] || o->n_lev < 3) return MLFMA_OK;
     CoreTimer tm(o);
     if (int r = tm.init()) return r;
-    auto refine = [&](int &knob, const float *alone, int nv) -> int {
-        float fastest = 1e30f;
-        for (int v = 0; v < nv; ++v)
-            if (alone[v] >= 0.f) fastest = std::min(fastest, alone[v]);
-        int cand[10], nc = 0;
-        for (int v = 0; v < nv; ++v)
-            if (alone[v] >= 0.f && alone[v] <= 1.25f * fastest) cand[nc++] = v;
+    // time each candidate value of `knob` (values below 10) in the core
+    auto pick = [&](int &knob, const int *cand, int nc) -> int {
         if (nc < 2) return MLFMA_OK;
         const int cur = knob;
         float t[10];
@@ -847,12 +868,25 @@ int refine_schedule(mlfma_ops_s *o)
         knob = (t[cur] < 1e30f && t[best] >= 0.997f * t[cur]) ? cur : best;
         return MLFMA_OK;
     };
+    auto refine = [&](int &knob, const float *alone, int nv) -> int {
+        float fastest = 1e30f;
+        for (int v = 0; v < nv; ++v)
+            if (alone[v] >= 0.f) fastest = std::min(fastest, alone[v]);
+        int cand[10], nc = 0;
+        for (int v = 0; v < nv; ++v)
+            if (alone[v] >= 0.f && alone[v] <= 1.25f * fastest) cand[nc++] = v;
+        return pick(knob, cand, nc);
+    };
     for (int l = o->n_lev; l >= 3; --l)
         if (int r = refine(o->lev[l].m2l_variant, o->lev[l].m2l_alone, 10)) return r;
     for (int l = o->n_lev - 1; l >= 3; --l) {
         DevLevel &P = o->lev[l];
         if (int r = refine(P.interp_variant, P.interp_alone, 5)) return r;
         if (int r = refine(P.anterp_variant, P.anterp_alone, 5)) return r;
+    }
+    if (o->near_fork >= 3) {
+        const int halves[2] = {0, 1};
+        if (int r = pick(o->near_split, halves, 2)) return r;
     }
     return MLFMA_OK;
 }
@@ -872,11 +906,11 @@ int tune_concurrent(mlfma_ops_s *o)
 {
     const int nl = o->n_lev;
     struct Pick {
-        int fork, share, late;
+        int fork, share, late, split;
         std::vector<int> m2l, interp, anterp;
     };
     auto save = [&]() {
-        Pick p{o->near_fork, o->m2l_share8, o->leaf_late, {}, {}, {}};
+        Pick p{o->near_fork, o->m2l_share8, o->leaf_late, o->near_split, {}, {}, {}};
         for (int l = 3; l <= nl; ++l) {
             p.m2l.push_back(o->lev[l].m2l_variant);
             p.interp.push_back(o->lev[l].interp_variant);
@@ -888,6 +922,7 @@ int tune_concurrent(mlfma_ops_s *o)
         o->near_fork = p.fork;
         o->m2l_share8 = p.share;
         o->leaf_late = p.late;
+        o->near_split = p.split;
         for (int l = 3; l <= nl; ++l) {
             o->lev[l].m2l_variant = p.m2l[l - 3];
             o->lev[l].interp_variant = p.interp[l - 3];
@@ -2043,6 +2078,7 @@ int mlfma_ops_variants(mlfma_ops_t o, int kernel, int32_t *out, int max_entries)
         if (max_entries >= 1) out[0] = o->side[0] ? o->near_fork : -1;
         if (max_entries >= 2) out[1] = o->side[0] ? o->m2l_share8 : -1;
         if (max_entries >= 3) out[2] = o->side[0] ? o->leaf_late : -1;
+        if (max_entries >= 4) out[3] = o->side[0] ? o->near_split : -1;
         return MLFMA_OK;
     }
     return fail(MLFMA_EINVAL, "ops_variants: kernel %d has no variants", kernel);
@@ -2083,6 +2119,9 @@ int mlfma_ops_set_variant(mlfma_ops_t o, int kernel, int level, int variant)
         } else if (level == 2) {
             if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad leaf M2L order %d", variant);
             o->leaf_late = variant;
+        } else if (level == 3) {
+            if (variant < 0 || variant > 1) return fail(MLFMA_EINVAL, "ops_set_variant: bad near-field split %d", variant);
+            o->near_split = variant;
         } else {
             // fork points 3 and 4 need that many M2Ms in the upward pass
             if (variant < 0 || variant > 2 + std::min(2, std::max(0, o->n_lev - 3)))

@@ -368,12 +368,13 @@ class Operators:
         kernel="p2p": the concurrent schedule, [where it forks the near field
         (1 at the start, 2 after C2M, 3 / 4 after the first / second M2M, 0 at
         the downward pass), eighths of the CUs the M2L workgroups of levels
-        > 3 may hold, 1 if the leaf M2L runs late (during the downward pass)];
-        [-1, -1, -1] on one stream.  set_variant(level, v, "p2p") sets the
-        share (level 1), the leaf M2L order (level 2) or the fork point
-        (level 0)."""
+        > 3 may hold, 1 if the leaf M2L runs late (during the downward pass),
+        1 if the near field forked after an M2M runs in two halves];
+        [-1, -1, -1, -1] on one stream.  set_variant(level, v, "p2p") sets
+        the share (level 1), the leaf M2L order (level 2), the near-field
+        split (level 3) or the fork point (level 0)."""
         nl = self.tree.info()["n_levels"]
-        out = np.full(3 if kernel == "p2p" else max(nl, 1), -1, np.int32)
+        out = np.full(4 if kernel == "p2p" else max(nl, 1), -1, np.int32)
         _check(_load().mlfma_ops_variants(self._h, KERNELS.index(kernel), out.ctypes.data,
                                           out.size), "mlfma_ops_variants")
         return out.tolist() if kernel == "p2p" else out[:nl].tolist()

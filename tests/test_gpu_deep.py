@@ -107,25 +107,28 @@ def test_deep_every_near_field_fork_point(c2):
     kernels with every dependency kept: results identical bit for bit."""
     torch = c2["torch"]
     ops = c2["gops"]
-    tuned, share, late = ops.variants("p2p")
+    tuned, share, late, split = ops.variants("p2p")
     rng = np.random.default_rng(91)
     n = c2["xyz"].shape[0]
     Q = (rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))).astype(np.complex64)
     try:
         ref = None
-        for fork, lt in ((1, 0), (2, 0), (3, 0), (4, 0), (0, 0), (1, 1), (4, 1), (0, 1)):
+        for fork, lt, sp in ((1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0), (0, 0, 0), (1, 1, 0),
+                             (4, 1, 0), (0, 1, 0), (3, 0, 1), (4, 1, 1)):
             ops.set_variant(0, fork, kernel="p2p")
             ops.set_variant(2, lt, kernel="p2p")
-            say("deep: near field forked at point", fork, "leaf M2L late", lt)
+            ops.set_variant(3, sp, kernel="p2p")
+            say("deep: near field forked at point", fork, "leaf M2L late", lt, "halves", sp)
             for rep in range(2):
                 got = _matvec(c2, Q, ops)
                 if ref is None:
                     ref = got
-                assert np.array_equal(got, ref), (fork, lt, rep)
+                assert np.array_equal(got, ref), (fork, lt, sp, rep)
     finally:
         ops.set_variant(0, tuned, kernel="p2p")
         ops.set_variant(1, share, kernel="p2p")
         ops.set_variant(2, late, kernel="p2p")
+        ops.set_variant(3, split, kernel="p2p")
 
 
 def test_deep_near_and_far_parts(c2):

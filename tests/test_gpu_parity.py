@@ -353,31 +353,35 @@ def test_concurrent_schedule_equals_one_stream(c1):
     n = c1["xyz"].shape[0]
     Q = (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))).astype(np.complex64)
     Qd = torch.from_numpy(Q).cuda()
-    tuned, share, late = ops.variants("p2p")
+    tuned, share, late, split = ops.variants("p2p")
     # (four levels: one M2M, so fork point 4 does not exist)
     assert tuned in (0, 1, 2, 3) and share in (4, 6, 7, 8) and late in (0, 1)
-    assert ops1.variants("p2p") == [-1, -1, -1]
+    assert split in (0, 1) and ops1.variants("p2p") == [-1, -1, -1, -1]
     try:
         # near field forked at the downward pass / start / after C2M /
         # after the M2M; M2L of levels > 3 on half, three quarters or all
         # of the CUs; the leaf M2L beside the upward pass or after the
         # coarser levels' M2L
-        for fork, sh, lt in ((0, 6, 0), (1, 6, 0), (2, 6, 0), (1, 4, 0), (2, 8, 0),
-                             (3, 6, 0), (3, 8, 0), (1, 6, 1), (0, 8, 1), (3, 7, 1)):
+        # (and the near field forked after the M2M in two halves)
+        for fork, sh, lt, sp in ((0, 6, 0, 0), (1, 6, 0, 0), (2, 6, 0, 0), (1, 4, 0, 0),
+                                 (2, 8, 0, 0), (3, 6, 0, 0), (3, 8, 0, 1), (1, 6, 1, 0),
+                                 (0, 8, 1, 0), (3, 7, 1, 0), (3, 4, 1, 1)):
             ops.set_variant(0, fork, kernel="p2p")
             ops.set_variant(1, sh, kernel="p2p")
             ops.set_variant(2, lt, kernel="p2p")
+            ops.set_variant(3, sp, kernel="p2p")
             for rep in range(3):
                 a = _run(c1, ops.matvec, Qd)
                 b = _run(c1, ops1.matvec, Qd)
-                assert np.array_equal(a, b), (fork, sh, lt, rep)
+                assert np.array_equal(a, b), (fork, sh, lt, sp, rep)
             fa = _run(c1, ops.field, Qd[:, 0].contiguous())
             fb = _run(c1, ops1.field, Qd[:, 0].contiguous())
-            assert np.array_equal(fa, fb), (fork, sh, lt)
+            assert np.array_equal(fa, fb), (fork, sh, lt, sp)
     finally:
         ops.set_variant(0, tuned, kernel="p2p")
         ops.set_variant(1, share, kernel="p2p")
         ops.set_variant(2, late, kernel="p2p")
+        ops.set_variant(3, split, kernel="p2p")
 
 
 def test_graph_replays_match_eager(c1):
@@ -426,7 +430,7 @@ def test_variant_and_schedule_limits(c1):
     bad = [
         (3, 10, "m2l"), (3, -1, "m2l"), (2, 0, "m2l"), (nl + 1, 0, "m2l"),
         (0, 4, "p2p"), (0, 5, "p2p"), (0, -1, "p2p"), (1, 0, "p2p"), (1, 9, "p2p"),
-        (2, 2, "p2p"), (2, -1, "p2p"),
+        (2, 2, "p2p"), (2, -1, "p2p"), (3, 2, "p2p"), (3, -1, "p2p"),
         (nl, 0, "interp"),
     ]
     for level, variant, kernel in bad:
